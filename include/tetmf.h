@@ -1,0 +1,201 @@
+/*
+ * tetmf — matrix-free Galerkin operators on unstructured tetrahedral meshes
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The operator is the cell-by-cell evaluation of eq. (5) (continuous
+ * Galerkin) and eq. (7) (SIPG discontinuous Galerkin) of Still, Fehn, Wall,
+ * Kronbichler, "Matrix-Free Evaluation Strategies for Continuous and
+ * Discontinuous Galerkin Discretizations on Unstructured Tetrahedral Grids"
+ * (arXiv 2509.10226):
+ *
+ *     A(u) = sum_e G_e^T E^T D_e E G_e u   (+ sum_f G_f^T E_f^T D_f E_f G_f u)
+ *
+ * G_e gathers the cell's DoF values, E tabulates reference gradients (and
+ * values) of the nodal basis at the quadrature points (eq. (6)), D_e applies
+ * the per-point geometry J^{-1} J^{-T} |det J| w_q and the coefficient
+ * kappa_q, E^T integrates against the test functions and G_e^T scatters back.
+ * The bilinear forms are eq. (2) (Poisson), eq. (3) (SIPG) and the
+ * Helmholtz-type form of eq. (16) (stiffness plus sigma times mass).
+ *
+ * Conventions shared by every entry point
+ *  - Status codes: 0 = OK, > 0 = non-fatal status, < 0 = error.  No entry
+ *    point throws or aborts; tetmf_last_error() describes the last failure
+ *    of the calling thread.
+ *  - "host" pointers are CPU memory, "device" pointers are GPU memory of the
+ *    op's device.  Device buffers passed in are owned by the caller.
+ *  - Work is enqueued on the given HIP stream (NULL = default stream) and
+ *    returns asynchronously unless stated otherwise; only launch errors are
+ *    reported by the return code.
+ *  - An op is not thread-safe: concurrent calls on one op race on its
+ *    internal scratch (the interface partial sums).  Use one op per stream.
+ *  - Library order: the op renumbers cells for locality (a Morton order of
+ *    cell centroids) and numbers DoFs by first touch in that order.
+ *    tetmf_op_numbering() exports the maps back to the user's order.
+ *  - Cell quadrature data (coefficients, coefficient gradients, source
+ *    samples) use the layout [n_q][n_cell] in library cell order; point q of
+ *    a cell is X0 + J x_q with J = [X1-X0 | X2-X0 | X3-X0] built from the
+ *    cell's vertices in the user's order (vertices are never reordered).
+ *  - Face quadrature data use [n_qf][n_face] with faces in canonical order
+ *    (lexicographic order of the sorted global vertex triples) and point q
+ *    at a + s_q (b - a) + t_q (c - a) for the sorted vertices a < b < c.
+ */
+#ifndef TETMF_H
+#define TETMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tetmf_mesh tetmf_mesh;
+typedef struct tetmf_op tetmf_op;
+
+enum tetmf_status {
+  TETMF_OK = 0,
+  TETMF_NOT_CONVERGED = 1,
+  TETMF_ERR_INVALID_ARGUMENT = -1,
+  TETMF_ERR_DEGENERATE_CELL = -2,
+  TETMF_ERR_NONCONFORMING_MESH = -3,
+  TETMF_ERR_UNSUPPORTED = -4,
+  TETMF_ERR_ALIAS = -5,
+  TETMF_ERR_OUT_OF_MEMORY = -6,
+  TETMF_ERR_DEVICE = -7
+};
+
+enum tetmf_kind { TETMF_CG = 0, TETMF_DG = 1 };
+enum tetmf_bc { TETMF_NEUMANN = 0, TETMF_DIRICHLET = 1 };
+/* arithmetic of the operator: FP64; FP32 (MFMA f32); BF16 operands of both
+ * products with FP32 accumulation and FP32 vectors */
+enum tetmf_precision { TETMF_F64 = 0, TETMF_F32 = 1, TETMF_BF16IN = 2 };
+enum tetmf_ordering { TETMF_ORDER_LOCALITY = 0, TETMF_ORDER_AS_GIVEN = 1 };
+
+/* Operator description (all host memory, copied by tetmf_op_create). */
+typedef struct {
+  int32_t kind;        /* tetmf_kind */
+  int32_t degree;      /* polynomial degree p, 1..3 (nodal equispaced Lagrange) */
+  int32_t bc;          /* CG: DIRICHLET constrains boundary DoFs (rows act as
+                          identity, v_c = u_c); DG: DIRICHLET adds the mirror
+                          boundary terms, NEUMANN adds none */
+  int32_t precision;   /* tetmf_precision */
+  int32_t ordering;    /* tetmf_ordering */
+  int32_t n_q;         /* cell rule: points [n_q][3] on the reference tet  */
+  const double* q_points;   /* (0,0,0),(1,0,0),(0,1,0),(0,0,1); weights sum */
+  const double* q_weights;  /* to 1/6 */
+  int32_t n_qf;        /* face rule (DG only): points [n_qf][2] on the      */
+  const double* qf_points;  /* reference triangle (0,0),(1,0),(0,1);        */
+  const double* qf_weights; /* weights sum to 1/2 */
+  double sigma;        /* mass coefficient of the Helmholtz-type form (0 = Poisson) */
+  double eta;          /* SIPG penalty factor: tau_F = eta (p+1)^2 |F| / min|K| */
+  int32_t device;      /* HIP device ordinal */
+} tetmf_op_desc;
+
+typedef struct {
+  int64_t n_dofs;      /* global DoFs (CG: continuous nodes; DG: 20 n_cell at p=3) */
+  int64_t n_free;      /* CG: unconstrained DoFs, numbered 0..n_free-1 */
+  int64_t n_cell, n_face, n_interior_face;
+  int32_t n_q, n_qf, n_dof_cell, precision;
+  int64_t n_blocks;    /* CG: cell blocks of one workgroup */
+  int64_t n_shared;    /* CG: free DoFs touched by more than one block */
+  int64_t n_partials;  /* CG: (block, shared DoF) pairs */
+  double flops_per_apply;  /* algorithmic work of one apply (method's count) */
+  double bytes_per_apply;  /* algorithmic HBM bytes of one apply */
+  int64_t device_bytes;    /* device memory held by the op */
+} tetmf_info;
+
+/* Mesh setup (Sec. 2.2 geometry; faces for eq. (7)).
+ * xyz: host [n_vert][3]; tets: host [n_cell][4] vertex ids.
+ * Errors: INVALID_ARGUMENT (sizes, ids out of range), DEGENERATE_CELL
+ * (|det J| <= 1e-12 (mean edge length)^3), NONCONFORMING_MESH (a triangle in
+ * more than two cells).  Inputs are copied; free with tetmf_mesh_destroy. */
+int tetmf_mesh_create(int64_t n_vert, const double* xyz, int64_t n_cell, const int32_t* tets,
+                      tetmf_mesh** out);
+void tetmf_mesh_destroy(tetmf_mesh* mesh);
+/* Number of faces (canonical order) and of interior faces. */
+int tetmf_mesh_faces(const tetmf_mesh* mesh, int64_t* n_face, int64_t* n_interior);
+
+/* Operator setup: DoF numbering, cell blocks, geometry G_e = |det J| J^{-1}
+ * J^{-T} computed in FP64 and rounded to the op precision, basis tables,
+ * face data.  Allocates device memory (OUT_OF_MEMORY on failure).
+ * UNSUPPORTED for a (degree, n_q, n_qf, precision, kind) combination with no
+ * compiled kernel.  The mesh may be destroyed afterwards. */
+int tetmf_op_create(const tetmf_mesh* mesh, const tetmf_op_desc* desc, tetmf_op** out);
+void tetmf_op_destroy(tetmf_op* op);
+int tetmf_op_info(const tetmf_op* op, tetmf_info* info);
+
+/* Maps from library order to user order (host buffers, any may be NULL):
+ *  cell_perm [n_cell]: user cell id of library cell i
+ *  dof_xyz   [n_dofs][3]: coordinates of each DoF (library numbering)
+ *  dof_cell  [n_dofs]: DG: user cell owning the DoF; CG: one user cell containing it */
+int tetmf_op_numbering(const tetmf_op* op, int32_t* cell_perm, double* dof_xyz, int32_t* dof_cell);
+
+/* Reorder per-point cell data from user layout [n_cell][n_q] (user cell
+ * order, FP64, device) to library layout [n_q][n_cell] in the op precision
+ * (FP32 for F32 and BF16IN), or back (to_user != 0; library layout in the op
+ * precision to user layout in FP64). */
+int tetmf_cell_data_layout(const tetmf_op* op, const void* src, void* dst, int to_user, void* stream);
+
+/* v = A(kappa) u  (eq. (5) CG / eq. (7) DG), deterministic: the result is
+ * bitwise reproducible for fixed inputs.
+ *  u, v: device [n_dofs] in the op precision (FP32 for BF16IN); must not
+ *        alias (ALIAS).
+ *  kappa_cell: device [n_q][n_cell] or NULL (kappa = 1).
+ *  kappa_face: DG only, device [n_qf][n_face] or NULL (kappa = 1).
+ *  CG DIRICHLET: constrained entries v_c = u_c; constrained u_c do not enter
+ *  the free rows (masked gather, Sec. 2.4). */
+int tetmf_apply(tetmf_op* op, const void* u, const void* kappa_cell, const void* kappa_face, void* v,
+                void* stream);
+
+/* Backward of v = A(kappa) u for an upstream gradient g = dL/dv (CG):
+ *  du = A^T g (= A g, the forms are symmetric) and
+ *  dkappa_cell[q][e] = w_q |det J_e| (grad u . grad g)(x_q),
+ * the derivative of g^T A(kappa) u.  du or dkappa_cell may be NULL.  Layouts
+ * as for tetmf_apply.  UNSUPPORTED for DG. */
+int tetmf_apply_backward(tetmf_op* op, const void* u, const void* g, const void* kappa_cell,
+                         const void* kappa_face, void* du, void* dkappa_cell, void* dkappa_face,
+                         void* stream);
+
+/* d = diag(A(kappa)) (CG), constrained entries 1.  Device [n_dofs]. */
+int tetmf_diagonal(tetmf_op* op, const void* kappa_cell, const void* kappa_face, void* d, void* stream);
+
+/* Load vector b_i = sum_e sum_q w_q |det J| f_{e,q} phi_i(x_q) (CG), zero on
+ * constrained rows.  f: device [n_q][n_cell] in the op precision or NULL
+ * (f = 1).  b: device [n_dofs]. */
+int tetmf_load_vector(tetmf_op* op, const void* f, void* b, void* stream);
+
+typedef struct {
+  double rtol;         /* stop when ||b - A x|| <= rtol ||b|| (FP64 true residual) */
+  double inner_rtol;   /* inner solve reduction per outer step (mixed precision) */
+  int32_t max_outer;
+  int32_t max_inner;   /* also the iteration cap of the plain FP64 PCG */
+  int32_t precond;     /* 0 = none, 1 = Jacobi (point diagonal of the operator) */
+} tetmf_solve_opts;
+
+typedef struct {
+  int32_t outer_its, inner_its;
+  double final_relres;  /* ||b - A64 x|| / ||b||, FP64 */
+  double seconds;
+} tetmf_solve_stats;
+
+/* Solve A64 x = b (CG, SPD operator) on the GPU.
+ *  op_inner == NULL: Jacobi-preconditioned conjugate gradients in FP64.
+ *  op_inner (F32 or BF16IN op on the same mesh): iterative refinement with
+ *  the FP64 residual r = b - A64 x, an inner Jacobi-PCG on A_inner d = r in
+ *  the inner precision (dot products accumulated in FP64), and x += d in
+ *  FP64 (mixed precision as in Sec. 4.1).
+ *  b, x: device FP64 [n_dofs]; x holds x0 on entry (warm start) and the
+ *  solution on exit.  kappa: device [n_q][n_cell] for each op's precision or
+ *  NULL.  Synchronises the stream.  Returns NOT_CONVERGED when the caps are
+ *  reached. */
+int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* op_inner, const void* kappa_inner,
+                const double* b, double* x, const tetmf_solve_opts* opts, tetmf_solve_stats* stats,
+                void* stream);
+
+const char* tetmf_status_string(int status);
+const char* tetmf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TETMF_H */

@@ -1,0 +1,328 @@
+"""Python binding of libtetmf (argument marshalling only).
+
+Every step of the operator runs in the HIP kernels of ``libtetmf.so``; this
+module converts torch tensors to device pointers and the current torch stream
+to a HIP stream, and turns status codes into exceptions.  PyTorch provides
+device memory and streams only.  There is no CPU fallback: if the shared
+library is missing, every entry point raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtetmf.so")
+_LIB = None
+
+CG, DG = 0, 1
+NEUMANN, DIRICHLET = 0, 1
+F64, F32, BF16IN = 0, 1, 2
+ORDER_LOCALITY, ORDER_AS_GIVEN = 0, 1
+
+_PREC = {"f64": F64, "f32": F32, "bf16in": BF16IN}
+_KIND = {"cg": CG, "dg": DG}
+_BC = {"neumann": NEUMANN, "dirichlet": DIRICHLET}
+_ORDER = {"locality": ORDER_LOCALITY, "as_given": ORDER_AS_GIVEN}
+
+
+class TetmfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tetmf status {status}: {msg}")
+        self.status = status
+
+
+class OpDesc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("degree", ctypes.c_int32), ("bc", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("ordering", ctypes.c_int32),
+        ("n_q", ctypes.c_int32), ("q_points", ctypes.c_void_p), ("q_weights", ctypes.c_void_p),
+        ("n_qf", ctypes.c_int32), ("qf_points", ctypes.c_void_p), ("qf_weights", ctypes.c_void_p),
+        ("sigma", ctypes.c_double), ("eta", ctypes.c_double), ("device", ctypes.c_int32),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("n_dofs", ctypes.c_int64), ("n_free", ctypes.c_int64), ("n_cell", ctypes.c_int64),
+        ("n_face", ctypes.c_int64), ("n_interior_face", ctypes.c_int64),
+        ("n_q", ctypes.c_int32), ("n_qf", ctypes.c_int32), ("n_dof_cell", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("n_blocks", ctypes.c_int64), ("n_shared", ctypes.c_int64), ("n_partials", ctypes.c_int64),
+        ("flops_per_apply", ctypes.c_double), ("bytes_per_apply", ctypes.c_double),
+        ("device_bytes", ctypes.c_int64),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("max_inner", ctypes.c_int32), ("precond", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("outer_its", ctypes.c_int32), ("inner_its", ctypes.c_int32),
+                ("final_relres", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+# exported C symbols and their signatures
+_SIGS = {
+    "tetmf_mesh_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "tetmf_mesh_destroy": (None, [ctypes.c_void_p]),
+    "tetmf_mesh_faces": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "tetmf_op_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(OpDesc), ctypes.POINTER(ctypes.c_void_p)]),
+    "tetmf_op_destroy": (None, [ctypes.c_void_p]),
+    "tetmf_op_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "tetmf_op_numbering": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "tetmf_cell_data_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                              ctypes.c_void_p]),
+    "tetmf_apply": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 5),
+    "tetmf_apply_backward": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 8),
+    "tetmf_diagonal": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "tetmf_load_vector": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
+    "tetmf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
+                                   ctypes.POINTER(SolveStats), ctypes.c_void_p]),
+    "tetmf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "tetmf_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib():
+    """Load libtetmf.so (built in-tree by ``_build.py``); raise if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run python paper_2509_10226_amd/_build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status < 0:
+        L = lib()
+        raise TetmfError(status, L.tetmf_last_error().decode())
+    return status
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """Host-side tetrahedral mesh (vertex coordinates and cell vertex lists)."""
+
+    def __init__(self, xyz, tets):
+        L = lib()
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.tets = np.ascontiguousarray(tets, dtype=np.int32)
+        if self.xyz.ndim != 2 or self.xyz.shape[1] != 3 or self.tets.ndim != 2 or self.tets.shape[1] != 4:
+            raise ValueError("xyz must be [n_vert, 3] and tets [n_cell, 4]")
+        h = ctypes.c_void_p()
+        _check(L.tetmf_mesh_create(self.xyz.shape[0], self.xyz.ctypes.data, self.tets.shape[0],
+                                   self.tets.ctypes.data, ctypes.byref(h)))
+        self._h = h
+        nf, ni = ctypes.c_int64(), ctypes.c_int64()
+        _check(L.tetmf_mesh_faces(h, ctypes.byref(nf), ctypes.byref(ni)))
+        self.n_face, self.n_interior_face = nf.value, ni.value
+
+    @property
+    def n_cell(self):
+        return self.tets.shape[0]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.tetmf_mesh_destroy(self._h)
+            self._h = None
+
+
+class Operator:
+    """Matrix-free operator A(kappa) on a mesh (see include/tetmf.h)."""
+
+    def __init__(self, mesh, degree, qrule, kind="cg", frule=None, precision="f64", bc="neumann",
+                 sigma=0.0, eta=1.0, ordering="locality", device=0):
+        L = lib()
+        qp, qw = (np.ascontiguousarray(a, dtype=np.float64) for a in qrule)
+        d = OpDesc()
+        d.kind = _KIND[kind]
+        d.degree = int(degree)
+        d.bc = _BC[bc]
+        d.precision = _PREC[precision]
+        d.ordering = _ORDER[ordering]
+        d.n_q = qw.size
+        d.q_points = qp.ctypes.data
+        d.q_weights = qw.ctypes.data
+        self._keep = [qp, qw]
+        if frule is not None:
+            fp, fw = (np.ascontiguousarray(a, dtype=np.float64) for a in frule)
+            d.n_qf = fw.size
+            d.qf_points = fp.ctypes.data
+            d.qf_weights = fw.ctypes.data
+            self._keep += [fp, fw]
+        d.sigma = float(sigma)
+        d.eta = float(eta)
+        d.device = int(device)
+        h = ctypes.c_void_p()
+        _check(L.tetmf_op_create(mesh._h, ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.kind, self.precision, self.degree = kind, precision, degree
+        self.device = int(device)
+        info = Info()
+        _check(L.tetmf_op_info(h, ctypes.byref(info)))
+        self.info = {k: getattr(info, k) for k, _ in Info._fields_}
+        self.n_dofs = self.info["n_dofs"]
+        self.n_free = self.info["n_free"]
+        self.n_cell = self.info["n_cell"]
+        self.n_face = self.info["n_face"]
+        self.n_q = self.info["n_q"]
+        self.n_qf = self.info["n_qf"]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _LIB is not None:
+            _LIB.tetmf_op_destroy(self._h)
+            self._h = None
+
+    @property
+    def dtype(self):
+        torch = _torch()
+        return torch.float64 if self.precision == "f64" else torch.float32
+
+    def numbering(self):
+        """(cell_perm [n_cell], dof_xyz [n_dofs, 3], dof_cell [n_dofs]) host arrays."""
+        cp = np.empty(self.n_cell, dtype=np.int32)
+        xyz = np.empty((self.n_dofs, 3), dtype=np.float64)
+        dc = np.empty(self.n_dofs, dtype=np.int32)
+        _check(lib().tetmf_op_numbering(self._h, cp.ctypes.data, xyz.ctypes.data, dc.ctypes.data))
+        return cp, xyz, dc
+
+    def _device(self):
+        torch = _torch()
+        return torch.device("cuda", self.device)
+
+    def cell_data_to_library(self, data_user):
+        """[n_cell, n_q] FP64 (user order) -> [n_q, n_cell] op dtype (library order), on the GPU."""
+        torch = _torch()
+        src = data_user.to(device=self._device(), dtype=torch.float64).contiguous()
+        if src.shape != (self.n_cell, self.n_q):
+            raise ValueError(f"expected [{self.n_cell}, {self.n_q}]")
+        dst = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=self._device())
+        _check(lib().tetmf_cell_data_layout(self._h, _ptr(src), _ptr(dst), 0, _stream()))
+        return dst
+
+    def cell_data_to_user(self, data_lib):
+        torch = _torch()
+        dst = torch.empty((self.n_cell, self.n_q), dtype=torch.float64, device=self._device())
+        _check(lib().tetmf_cell_data_layout(self._h, _ptr(data_lib, self.dtype, self.n_cell * self.n_q),
+                                            _ptr(dst), 1, _stream()))
+        return dst
+
+    def apply(self, u, kappa_cell=None, kappa_face=None, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
+        _check(lib().tetmf_apply(self._h, _ptr(u, self.dtype, self.n_dofs, "u"),
+                                 _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                 _ptr(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
+                                 _ptr(out, self.dtype, self.n_dofs, "v"), _stream()))
+        return out
+
+    def backward(self, u, g, kappa_cell=None, need_du=True, need_dkappa=True):
+        torch = _torch()
+        du = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device()) if need_du else None
+        dk = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=self._device()) if need_dkappa else None
+        _check(lib().tetmf_apply_backward(self._h, _ptr(u, self.dtype, self.n_dofs, "u"),
+                                          _ptr(g, self.dtype, self.n_dofs, "g"),
+                                          _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                          None, _ptr(du), _ptr(dk), None, _stream()))
+        return du, dk
+
+    def diagonal(self, kappa_cell=None):
+        torch = _torch()
+        d = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
+        _check(lib().tetmf_diagonal(self._h, _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                    None, _ptr(d), _stream()))
+        return d
+
+    def load_vector(self, f=None):
+        torch = _torch()
+        b = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
+        _check(lib().tetmf_load_vector(self._h, _ptr(f, self.dtype, self.n_q * self.n_cell, "f"), _ptr(b),
+                                       _stream()))
+        return b
+
+    def solve(self, b, x0=None, kappa=None, inner=None, kappa_inner=None, rtol=1e-10, inner_rtol=1e-4,
+              max_outer=50, max_inner=5000, precond="jacobi"):
+        """Solve A x = b (see tetmf_solve).  Returns (x, stats dict, converged)."""
+        torch = _torch()
+        x = torch.zeros(self.n_dofs, dtype=torch.float64, device=self._device()) if x0 is None else x0.clone()
+        o = SolveOpts(rtol, inner_rtol, max_outer, max_inner, 1 if precond == "jacobi" else 0)
+        st = SolveStats()
+        status = _check(lib().tetmf_solve(
+            self._h, _ptr(kappa, torch.float64, self.n_q * self.n_cell, "kappa"),
+            inner._h if inner is not None else None,
+            _ptr(kappa_inner, inner.dtype if inner is not None else None, None, "kappa_inner"),
+            _ptr(b, torch.float64, self.n_dofs, "b"), _ptr(x, torch.float64, self.n_dofs, "x"),
+            ctypes.byref(o), ctypes.byref(st), _stream()))
+        stats = {k: getattr(st, k) for k, _ in SolveStats._fields_}
+        return x, stats, status == 0
+
+
+def _autograd():
+    torch = _torch()
+
+    class ApplyFunction(torch.autograd.Function):
+        """v = A(kappa) u with a hand-written backward kernel:
+        dL/du = A^T dL/dv and dL/dkappa_q = w_q |det J| grad u . grad (dL/dv)."""
+
+        @staticmethod
+        def forward(ctx, u, kappa, op):
+            ctx.op = op
+            ctx.save_for_backward(u, kappa)
+            return op.apply(u.contiguous(), kappa.contiguous())
+
+        @staticmethod
+        def backward(ctx, gv):
+            u, kappa = ctx.saved_tensors
+            du, dk = ctx.op.backward(u, gv.contiguous(), kappa, need_du=ctx.needs_input_grad[0],
+                                     need_dkappa=ctx.needs_input_grad[1])
+            return du, dk, None
+
+    return ApplyFunction
+
+
+_APPLY_FN = None
+
+
+def apply_autograd(op, u, kappa):
+    """Differentiable v = A(kappa) u (kappa in library layout [n_q, n_cell])."""
+    global _APPLY_FN
+    if _APPLY_FN is None:
+        _APPLY_FN = _autograd()
+    return _APPLY_FN.apply(u, kappa, op)

@@ -1,0 +1,95 @@
+// Internal declarations shared by the host setup (tetmf.cpp) and the HIP
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tetmf {
+
+// Cells handled by one workgroup pass of the continuous-Galerkin kernel.  The
+// block's DoFs are staged in LDS; DoFs touched only by one block are written
+// directly, the others go through per-block partial sums (see cg_reduce).
+constexpr int kBlockCells = 256;
+// Cells per MFMA tile (the N dimension of the 16x16 matrix-core products).
+constexpr int kTile = 16;
+constexpr int kWaves = 8;                  // waves per workgroup
+constexpr int kThreads = kWaves * 64;      // threads per workgroup
+constexpr int kTilesPerWave = kBlockCells / kTile / kWaves;
+
+enum Mode { MODE_APPLY = 0, MODE_BACKWARD = 1, MODE_DIAG = 2, MODE_LOAD = 3 };
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16 = 2 };
+
+// Device-side description of a continuous-Galerkin operator.  All pointers are
+// device memory owned by the op.  "ncp" is the cell count padded to a whole
+// number of blocks; per-cell arrays are [field][ncp].
+struct CGDev {
+  int n_cell, ncp, n_dofs, n_free, n_blocks, n_shared;
+  int nq;                 // quadrature points (<= 4 * MT of the kernel)
+  int nbd_max;            // largest number of DoFs of one block
+  double sigma;           // mass coefficient
+  const void* geo;        // [7][ncp]: G00 G01 G02 G11 G12 G22 (= |detJ| J^-1 J^-T), |detJ|
+  const void* tab;        // basis table, layout chosen by the precision (see kernels.hip)
+  const void* qw;         // [4*MT] quadrature weights, zero beyond nq
+  const int* blk_priv_start;  // [n_blocks] first id of the block's private DoF range
+  const int* blk_npriv;       // [n_blocks] private DoFs of the block
+  const int* blk_nbd;         // [n_blocks] DoFs touched by the block
+  const int* blk_other_off;   // [n_blocks] offset into other_gid / other_pslot
+  const int* blk_ptr_off;     // [n_blocks] offset into slot_ptr
+  const int* other_gid;       // global id of each non-private block DoF
+  const int* other_pslot;     // partial-sum slot of each non-private block DoF (-1: constrained)
+  const uint16_t* lidx;       // [ndof][ncp] block-local DoF index of (local node, cell)
+  const uint16_t* pos;        // [ndof][ncp] LDS slot of (local node, cell), grouped by block DoF
+  const uint16_t* slot_ptr;   // per block [nbd + 1] slot ranges of the block DoFs
+  const int* sh_gid;          // [n_shared] global id of DoFs shared between blocks
+  const int* sh_ptr;          // [n_shared + 1] their contiguous partial-sum ranges
+  void* partials;             // [n_partials] scratch
+};
+
+// Device-side description of a discontinuous-Galerkin (SIPG) operator.
+struct DGDev {
+  int n_cell, ncp, n_face;
+  int nq, nqf;
+  int dirichlet;
+  double sigma;
+  const void* geo;        // [7][ncp]
+  const void* tab;        // cell basis table
+  const void* ftab;       // face basis table (reference face z = 0)
+  const void* qw;         // [4*MT]
+  const void* fw;         // [4*MTF] face weights
+  const int* nb;          // [4][ncp] library id of the neighbour across local face f, -1 on the boundary
+  const int* fid;         // [4][ncp] canonical face id
+  const int* code;        // [4][ncp] own relabelling | neighbour relabelling << 8
+  const void* fgeo;       // [8][4][ncp] b_own(3) b_nb(3) 2|F| tau
+  const uint8_t* perm;    // [24][ndof] node permutation of each vertex relabelling
+};
+
+// Launchers (kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_cg(const CGDev& d, int prec, int ndof, int mt, int mode, const void* u, const void* g,
+                     const void* kappa, void* out, void* dkappa, hipStream_t s, bool* supported);
+hipError_t launch_dg(const DGDev& d, int prec, int ndof, int mt, int mtf, const void* u,
+                     const void* kappa_cell, const void* kappa_face, void* v, hipStream_t s,
+                     bool* supported);
+hipError_t launch_layout(int prec, int to_user, const int* cell_perm, int n_cell, int nq,
+                         const void* src, void* dst, hipStream_t s);
+
+// Vector kernels used by the solver (kernels.hip).
+hipError_t vec_fill(int prec, void* x, double value, int64_t n, hipStream_t s);
+// Deterministic dot product: per-workgroup partial sums in FP64, reduced in
+// fixed order by a single workgroup into *result (device FP64).
+hipError_t vec_dot(int prec, const void* x, const void* y, int64_t n, double* partial, double* result,
+                   hipStream_t s);
+hipError_t vec_cast(int prec_src, const void* src, int prec_dst, void* dst, int64_t n, hipStream_t s);
+// r = b - a (FP64)
+hipError_t vec_sub(const double* b, const double* a, double* r, int64_t n, hipStream_t s);
+// PCG steps with device-resident scalars (see kernels.hip).
+hipError_t pcg_update_xr(int prec, void* x, void* r, const void* p, const void* q, const double* rz,
+                         const double* pq, int64_t n, hipStream_t s);
+hipError_t pcg_precond(int prec, void* z, const void* r, const void* dinv, int64_t n, hipStream_t s);
+hipError_t pcg_update_p(int prec, void* p, const void* z, const double* rz_new, const double* rz_old,
+                        int64_t n, hipStream_t s);
+hipError_t vec_recip(int prec, void* d, int64_t n, hipStream_t s);
+hipError_t vec_axpy_f64(double* x, const void* d, int prec_d, int64_t n, hipStream_t s);
+
+}  // namespace tetmf
