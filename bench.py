@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput of the matrix-free operator apply (DoFs/s per apply) and its
+roofline fraction on one MI355X.
+
+Workload (one "step" = one application v = A(kappa) u, i.e. gather,
+interpolate, point operator, integrate and scatter over the whole mesh):
+continuous Galerkin P3 Poisson with a lognormal (mu = 0, sigma = 1)
+coefficient per quadrature point on the unit cube split into 64^3 cubes x 6
+Kuhn tetrahedra (1,572,864 cells, 7,189,057 DoFs), interior vertices
+jittered by up to 0.15 h (seed 0), symmetric 24-point degree-6 cell rule,
+random input vector.  ``value`` is the FP64 apply; the FP32 (matrix-core
+f32) apply on the same inputs is reported beside it.
+
+The roofline object refers to the dominant kernel (the cell kernel of the
+apply): algorithmic flops per launch (the paper's count, eq. (9), extended
+to a per-point coefficient) divided by its average duration, measured with
+HIP events on the stream the kernel runs on.  ``traffic`` is the HBM byte
+count per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE counters scaled by a
+copy-kernel calibration (profiles/), or null when the kernel source changed
+since the counters were taken.
+
+The CPU baseline is the oracle as it stands (FP64 sparse assembly plus one
+sparse matrix-vector product) timed on a bounded sample of the same workload
+(20^3 x 6 cells).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense matrix-core peaks
+PEAK_HBM_GBS = 8000.0
+METRIC = "DoFs/s per operator apply, p=3 CG, FP64 vs FP32-MFMA; % of roofline"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_apply_p3_n64_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2509_10226_amd", "csrc", "kernels.hip")
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(prec):
+    """Calibrated HBM bytes per launch from the committed counter summary, or None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_hash():
+        return None
+    key = f"traffic_bytes_per_launch_{prec}"
+    return float(vals[key]) if key in vals else None
+
+
+def build_workload(n, seed=0):
+    import synth
+    xyz, tets = synth.kuhn_cube_mesh(n, 0.15, seed)
+    qp, qw = synth.tet_rule(6)
+    kap = synth.lognormal(seed, synth.STREAM_KAPPA_CELL, (tets.shape[0], qw.size), mu=0.0, sigma=1.0)
+    return xyz, tets, qp, qw, kap
+
+
+def time_gpu(op, kl, u, steps, warmup):
+    import torch
+    out = torch.empty_like(u)
+    for _ in range(warmup):
+        op.apply(u, kl, out=out)
+    torch.cuda.synchronize()
+    op.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op.apply(u, kl, out=out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    op.profile(False)
+    ms_kernel, launches = op.profile_read()
+    assert launches == steps
+    return (t1 - t0) * 1e3 / steps, ms_kernel / launches, out
+
+
+def roofline(op, prec, avg_ms):
+    flops = op.info["flops_per_apply"]
+    bytes_alg = op.info["bytes_per_apply"]
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    traffic = read_traffic(prec)
+    return {
+        "bound": "mfma",
+        "achieved": round(achieved, 3),
+        "peak": PEAK_TFLOPS[prec],
+        "unit": "TFLOP/s",
+        "frac": round(achieved / PEAK_TFLOPS[prec], 4),
+        "traffic": traffic,
+        "algorithmic_flops": flops,
+        "algorithmic_bytes": bytes_alg,
+        "hbm_achieved_GBs": round(bytes_alg / (avg_ms * 1e-3) / 1e9, 1),
+        "hbm_frac": round(bytes_alg / (avg_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "kernel_ms": round(avg_ms, 5),
+    }
+
+
+def cpu_baseline(n_sample=20):
+    """The oracle (sparse FP64 assembly + SpMV, numpy/scipy, one thread) on a sample."""
+    import numpy as np
+
+    import oracle
+    import synth
+    xyz, tets, qp, qw, kap = build_workload(n_sample)
+    t0 = time.perf_counter()
+    A, d = oracle.assemble_cg(xyz, tets, 3, qp, qw, kappa=kap)
+    t1 = time.perf_counter()
+    u = synth.uniform(0, synth.STREAM_U, A.shape[0])
+    reps = 10
+    for _ in range(reps):
+        y = A @ u
+    t2 = time.perf_counter()
+    t_spmv = (t2 - t1) / reps
+    nd = A.shape[0]
+    return {
+        "value": round(nd / ((t1 - t0) + t_spmv), 1),
+        "unit": "DoFs/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"CG P3 lognormal(0,1) kappa, {n_sample}^3x6 Kuhn tets ({tets.shape[0]} cells, {nd} DoFs): "
+                   f"oracle FP64 assembly {t1 - t0:.2f} s + one CSR SpMV {t_spmv * 1e3:.2f} ms "
+                   f"(nnz {A.nnz}); value = DoFs / (assembly + SpMV)"),
+        "spmv_only_value": round(nd / t_spmv, 1),
+        "assembly_s": round(t1 - t0, 3),
+        "checksum": float(np.abs(y).sum()),
+    }
+
+
+def copy_calibration(mib=1024, reps=3):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * 1024 * 1024 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "reps": reps}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=64, help="cubes per axis (64 = the measured workload)")
+    ap.add_argument("--precisions", default="f64,f32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the operator shards by "
+              "cell partition with one halo exchange per apply, which this build does not run).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2509_10226_amd as tm
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    dev = torch.device("cuda", 0)
+    xyz, tets, qp, qw, kap = build_workload(args.n)
+    t_setup = time.perf_counter()
+    mesh = tm.Mesh(xyz, tets)
+    results = {}
+    for prec in args.precisions.split(","):
+        op = tm.Operator(mesh, 3, (qp, qw), precision=prec)
+        setup_s = time.perf_counter() - t_setup
+        kl = op.cell_data_to_library(torch.from_numpy(kap).to(dev))
+        g = torch.Generator(device="cpu").manual_seed(2)
+        u = (torch.rand(op.n_dofs, generator=g, dtype=torch.float64) * 2 - 1).to(dev, op.dtype)
+        ms_step, ms_kernel, out = time_gpu(op, kl, u, args.steps, args.warmup)
+        results[prec] = {
+            "value": op.n_dofs / (ms_step * 1e-3),
+            "ms_per_step": ms_step,
+            "roofline": roofline(op, prec, ms_kernel),
+            "n_dofs": op.n_dofs,
+            "n_cell": op.n_cell,
+            "setup_s": round(setup_s, 2),
+            "blocks": op.info["n_blocks"],
+            "shared_dofs": op.info["n_shared"],
+            "partials": op.info["n_partials"],
+        }
+        del op
+        t_setup = time.perf_counter()
+    main_prec = "f64" if "f64" in results else next(iter(results))
+    r = results[main_prec]
+    line = {
+        "metric": METRIC,
+        "value": round(r["value"], 1),
+        "unit": "DoFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": main_prec,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"CG P3 Poisson apply, lognormal(0,1) kappa per quadrature point, {args.n}^3x6 Kuhn tets "
+                         f"jittered 0.15h seed 0 ({r['n_cell']} cells, {r['n_dofs']} DoFs), 24-point degree-6 rule"),
+            "n_cell": r["n_cell"],
+            "n_dofs": r["n_dofs"],
+            "n_q": 24,
+            "ordering": "locality (Morton)",
+            "parallelism": "single GPU",
+        },
+        "roofline": r["roofline"],
+    }
+    for prec, rr in results.items():
+        if prec != main_prec:
+            line[prec] = {"value": round(rr["value"], 1), "ms_per_step": round(rr["ms_per_step"], 5),
+                          "roofline": rr["roofline"]}
+    line["setup_s"] = r["setup_s"]
+    line["blocks"] = {"n_blocks": r["blocks"], "shared_dofs": r["shared_dofs"], "partials": r["partials"]}
+    if not args.no_cpu_baseline and args.n == 64:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -192,6 +192,16 @@ int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* op_inner, const v
                 const double* b, double* x, const tetmf_solve_opts* opts, tetmf_solve_stats* stats,
                 void* stream);
 
+/* Measurement aid.  While enabled, the op records a HIP event pair on the
+ * caller's stream around every launch of its main kernel (the cell kernel of
+ * apply, backward, diagonal and load vector; the cell-and-face kernel for
+ * DG).  tetmf_op_profile(op, 1) starts a new measurement (events are created
+ * on demand and reused), tetmf_op_profile(op, 0) stops recording.
+ * tetmf_op_profile_read synchronises on the recorded events and returns the
+ * summed kernel time in milliseconds and the number of launches recorded. */
+int tetmf_op_profile(tetmf_op* op, int enable);
+int tetmf_op_profile_read(tetmf_op* op, double* total_ms, int64_t* launches);
+
 const char* tetmf_status_string(int status);
 const char* tetmf_last_error(void);
 

@@ -84,6 +84,9 @@ _SIGS = {
     "tetmf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
                                    ctypes.POINTER(SolveStats), ctypes.c_void_p]),
+    "tetmf_op_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "tetmf_op_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_int64)]),
     "tetmf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tetmf_last_error": (ctypes.c_char_p, []),
 }
@@ -292,6 +295,23 @@ class Operator:
             ctypes.byref(o), ctypes.byref(st), _stream()))
         stats = {k: getattr(st, k) for k, _ in SolveStats._fields_}
         return x, stats, status == 0
+
+
+def _profile_methods():
+    def profile(self, enable=True):
+        """Start (or stop) recording HIP events around the op's main kernel."""
+        _check(lib().tetmf_op_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed main-kernel milliseconds, launches) since profiling started."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().tetmf_op_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+    Operator.profile = profile
+    Operator.profile_read = profile_read
+
+
+_profile_methods()
 
 
 def _autograd():

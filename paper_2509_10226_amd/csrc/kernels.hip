@@ -314,7 +314,7 @@ __global__ void __launch_bounds__(256) cg_combine(CGDev d, const T* __restrict__
 
 template <typename T, int NDOF, int MT, int MODE>
 hipError_t launch_cg_t(const CGDev& d, const void* u, const void* g, const void* kappa, void* out, void* dk,
-                       hipStream_t s) {
+                       hipStream_t s, hipEvent_t* ev) {
   constexpr int NROW = MT * 16;
   constexpr int NDP = NDOF + 1;
   const int bufn = std::max(kBlockCells * NDOF, (MODE == MODE_BACKWARD ? 2 : 1) * d.nbd_max);
@@ -326,9 +326,11 @@ hipError_t launch_cg_t(const CGDev& d, const void* u, const void* g, const void*
   auto kern = cg_kernel<T, NDOF, MT, MODE>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)g, (const T*)kappa, (T*)out,
                      (T*)dk);
   e = hipGetLastError();
+  if (ev) (void)hipEventRecord(ev[1], s);
   if (e != hipSuccess || out == nullptr) return e;
   const int nfix = d.n_shared + (d.n_dofs - d.n_free);
   if (nfix > 0) {
@@ -341,32 +343,32 @@ hipError_t launch_cg_t(const CGDev& d, const void* u, const void* g, const void*
 
 template <typename T, int NDOF, int MT>
 hipError_t launch_cg_mode(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
-                          void* dk, hipStream_t s) {
+                          void* dk, hipStream_t s, hipEvent_t* ev) {
   switch (mode) {
-    case MODE_APPLY: return launch_cg_t<T, NDOF, MT, MODE_APPLY>(d, u, g, kappa, out, dk, s);
-    case MODE_BACKWARD: return launch_cg_t<T, NDOF, MT, MODE_BACKWARD>(d, u, g, kappa, out, dk, s);
-    case MODE_DIAG: return launch_cg_t<T, NDOF, MT, MODE_DIAG>(d, u, g, kappa, out, dk, s);
-    default: return launch_cg_t<T, NDOF, MT, MODE_LOAD>(d, u, g, kappa, out, dk, s);
+    case MODE_APPLY: return launch_cg_t<T, NDOF, MT, MODE_APPLY>(d, u, g, kappa, out, dk, s, ev);
+    case MODE_BACKWARD: return launch_cg_t<T, NDOF, MT, MODE_BACKWARD>(d, u, g, kappa, out, dk, s, ev);
+    case MODE_DIAG: return launch_cg_t<T, NDOF, MT, MODE_DIAG>(d, u, g, kappa, out, dk, s, ev);
+    default: return launch_cg_t<T, NDOF, MT, MODE_LOAD>(d, u, g, kappa, out, dk, s, ev);
   }
 }
 
 template <typename T>
 hipError_t launch_cg_shape(const CGDev& d, int ndof, int mt, int mode, const void* u, const void* g,
-                           const void* kappa, void* out, void* dk, hipStream_t s, bool* supported) {
+                           const void* kappa, void* out, void* dk, hipStream_t s, bool* supported, hipEvent_t* ev) {
   *supported = true;
-  if (ndof == 4 && mt == 1) return launch_cg_mode<T, 4, 1>(d, mode, u, g, kappa, out, dk, s);
-  if (ndof == 10 && mt == 1) return launch_cg_mode<T, 10, 1>(d, mode, u, g, kappa, out, dk, s);
-  if (ndof == 10 && mt == 4) return launch_cg_mode<T, 10, 4>(d, mode, u, g, kappa, out, dk, s);
-  if (ndof == 20 && mt == 4) return launch_cg_mode<T, 20, 4>(d, mode, u, g, kappa, out, dk, s);
-  if (ndof == 20 && mt == 6) return launch_cg_mode<T, 20, 6>(d, mode, u, g, kappa, out, dk, s);
+  if (ndof == 4 && mt == 1) return launch_cg_mode<T, 4, 1>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 10 && mt == 1) return launch_cg_mode<T, 10, 1>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 10 && mt == 4) return launch_cg_mode<T, 10, 4>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 20 && mt == 4) return launch_cg_mode<T, 20, 4>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 20 && mt == 6) return launch_cg_mode<T, 20, 6>(d, mode, u, g, kappa, out, dk, s, ev);
   *supported = false;
   return hipSuccess;
 }
 
 hipError_t launch_cg(const CGDev& d, int prec, int ndof, int mt, int mode, const void* u, const void* g,
-                     const void* kappa, void* out, void* dk, hipStream_t s, bool* supported) {
-  if (prec == PREC_F64) return launch_cg_shape<double>(d, ndof, mt, mode, u, g, kappa, out, dk, s, supported);
-  if (prec == PREC_F32) return launch_cg_shape<float>(d, ndof, mt, mode, u, g, kappa, out, dk, s, supported);
+                     const void* kappa, void* out, void* dk, hipStream_t s, bool* supported, hipEvent_t* ev) {
+  if (prec == PREC_F64) return launch_cg_shape<double>(d, ndof, mt, mode, u, g, kappa, out, dk, s, supported, ev);
+  if (prec == PREC_F32) return launch_cg_shape<float>(d, ndof, mt, mode, u, g, kappa, out, dk, s, supported, ev);
   *supported = false;
   return hipSuccess;
 }
@@ -535,7 +537,8 @@ __global__ void __launch_bounds__(kThreads) dg_kernel(DGDev d, const T* __restri
 }
 
 template <typename T, int NDOF, int MT, int MTF>
-hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void* kf, void* v, hipStream_t s) {
+hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void* kf, void* v, hipStream_t s,
+                       hipEvent_t* ev) {
   constexpr int NDP = NDOF + 1;
   const size_t lds = (size_t)((MT + MTF) * 16 * NDP + kWaves * kTile * NDOF) * sizeof(T) + 24 * NDOF * sizeof(int);
   const int ntiles = d.ncp / kTile;
@@ -544,25 +547,28 @@ hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void
   auto kern = dg_kernel<T, NDOF, MT, MTF>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)kc, (const T*)kf, (T*)v);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (ev) (void)hipEventRecord(ev[1], s);
+  return e;
 }
 
 template <typename T>
 hipError_t launch_dg_shape(const DGDev& d, int ndof, int mt, int mtf, const void* u, const void* kc,
-                           const void* kf, void* v, hipStream_t s, bool* supported) {
+                           const void* kf, void* v, hipStream_t s, bool* supported, hipEvent_t* ev) {
   *supported = true;
-  if (ndof == 4 && mt == 1 && mtf == 1) return launch_dg_t<T, 4, 1, 1>(d, u, kc, kf, v, s);
-  if (ndof == 10 && mt == 4 && mtf == 2) return launch_dg_t<T, 10, 4, 2>(d, u, kc, kf, v, s);
-  if (ndof == 20 && mt == 6 && mtf == 3) return launch_dg_t<T, 20, 6, 3>(d, u, kc, kf, v, s);
+  if (ndof == 4 && mt == 1 && mtf == 1) return launch_dg_t<T, 4, 1, 1>(d, u, kc, kf, v, s, ev);
+  if (ndof == 10 && mt == 4 && mtf == 2) return launch_dg_t<T, 10, 4, 2>(d, u, kc, kf, v, s, ev);
+  if (ndof == 20 && mt == 6 && mtf == 3) return launch_dg_t<T, 20, 6, 3>(d, u, kc, kf, v, s, ev);
   *supported = false;
   return hipSuccess;
 }
 
 hipError_t launch_dg(const DGDev& d, int prec, int ndof, int mt, int mtf, const void* u, const void* kc,
-                     const void* kf, void* v, hipStream_t s, bool* supported) {
-  if (prec == PREC_F64) return launch_dg_shape<double>(d, ndof, mt, mtf, u, kc, kf, v, s, supported);
-  if (prec == PREC_F32) return launch_dg_shape<float>(d, ndof, mt, mtf, u, kc, kf, v, s, supported);
+                     const void* kf, void* v, hipStream_t s, bool* supported, hipEvent_t* ev) {
+  if (prec == PREC_F64) return launch_dg_shape<double>(d, ndof, mt, mtf, u, kc, kf, v, s, supported, ev);
+  if (prec == PREC_F32) return launch_dg_shape<float>(d, ndof, mt, mtf, u, kc, kf, v, s, supported, ev);
   *supported = false;
   return hipSuccess;
 }

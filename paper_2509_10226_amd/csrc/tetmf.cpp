@@ -366,6 +366,22 @@ struct tetmf_op {
   int64_t mesh_nc = 0, mesh_nv = 0;
   // solver scratch (allocated on first solve)
   std::vector<DevBuf> solve_bufs;
+  // kernel timing (tetmf_op_profile)
+  bool profiling = false;
+  std::vector<hipEvent_t> events;  // pairs
+  size_t events_used = 0;          // pairs recorded
+
+  hipEvent_t* next_events() {
+    if (!profiling) return nullptr;
+    if (2 * events_used + 2 > events.size()) {
+      hipEvent_t a, b;
+      check_hip(hipEventCreate(&a), "hipEventCreate");
+      check_hip(hipEventCreate(&b), "hipEventCreate");
+      events.push_back(a);
+      events.push_back(b);
+    }
+    return &events[2 * events_used++];
+  }
 
   ~tetmf_op() {
     int cur = 0;
@@ -373,6 +389,7 @@ struct tetmf_op {
     (void)hipSetDevice(device);
     for (auto& b : bufs) (void)hipFree(b.p);
     for (auto& b : solve_bufs) (void)hipFree(b.p);
+    for (auto e : events) (void)hipEventDestroy(e);
     (void)hipSetDevice(cur);
   }
 
@@ -1023,7 +1040,7 @@ int run_cg(tetmf_op* op, int mode, const void* u, const void* g, const void* kap
   DeviceScope ds(op->device);
   bool supported = true;
   hipError_t e = launch_cg(op->cg, kernel_prec(op), op->ndof, op->mt, mode, u, g, kappa, out, dk,
-                           (hipStream_t)stream, &supported);
+                           (hipStream_t)stream, &supported, op->next_events());
   if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no kernel instantiation for this operator");
   check_hip(e, "kernel launch");
   return TETMF_OK;
@@ -1055,7 +1072,7 @@ extern "C" int tetmf_apply(tetmf_op* op, const void* u, const void* kappa_cell, 
     DeviceScope ds(op->device);
     bool supported = true;
     hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->mt, op->mtf, u, kappa_cell, kappa_face, v,
-                             (hipStream_t)stream, &supported);
+                             (hipStream_t)stream, &supported, op->next_events());
     if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
     check_hip(e, "kernel launch");
     return TETMF_OK;
@@ -1242,6 +1259,32 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
     }
     if (status != TETMF_OK) g_last_error = "tetmf_solve: iteration caps reached";
     return status;
+  });
+}
+
+extern "C" int tetmf_op_profile(tetmf_op* op, int enable) {
+  return guarded([&]() -> int {
+    if (!op) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_op_profile: NULL op");
+    if (enable) op->events_used = 0;
+    op->profiling = enable != 0;
+    return TETMF_OK;
+  });
+}
+
+extern "C" int tetmf_op_profile_read(tetmf_op* op, double* total_ms, int64_t* launches) {
+  return guarded([&]() -> int {
+    if (!op || !total_ms || !launches) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_op_profile_read: NULL argument");
+    DeviceScope ds(op->device);
+    double sum = 0;
+    for (size_t i = 0; i < op->events_used; ++i) {
+      check_hip(hipEventSynchronize(op->events[2 * i + 1]), "hipEventSynchronize");
+      float ms = 0;
+      check_hip(hipEventElapsedTime(&ms, op->events[2 * i], op->events[2 * i + 1]), "hipEventElapsedTime");
+      sum += ms;
+    }
+    *total_ms = sum;
+    *launches = (int64_t)op->events_used;
+    return TETMF_OK;
   });
 }
 
