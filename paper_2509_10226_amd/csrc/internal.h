@@ -67,10 +67,10 @@ struct DGDev {
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 // ev: NULL, or two events recorded on s just before and after the main kernel.
-hipError_t launch_cg(const CGDev& d, int prec, int ndof, int mt, int mode, const void* u, const void* g,
+hipError_t launch_cg(const CGDev& d, int prec, int ndof, int nq, int mode, const void* u, const void* g,
                      const void* kappa, void* out, void* dkappa, hipStream_t s, bool* supported,
                      hipEvent_t* ev);
-hipError_t launch_dg(const DGDev& d, int prec, int ndof, int mt, int mtf, const void* u,
+hipError_t launch_dg(const DGDev& d, int prec, int ndof, int nq, int nqf, const void* u,
                      const void* kappa_cell, const void* kappa_face, void* v, hipStream_t s,
                      bool* supported, hipEvent_t* ev);
 hipError_t launch_layout(int prec, int to_user, const int* cell_perm, int n_cell, int nq,

@@ -57,49 +57,84 @@ struct Mfma<float> {
   __device__ static constexpr int row_r(int i) { return i & 3; }
 };
 
-// T[(point 4t+g, comp r), cell] = sum_j tab[(point, comp), j] U[j, cell] for t < MT.
-// U operand: lane supplies U[4s + g][cell c16] in ub[s].
-template <typename T, int NDOF, int MT>
-__device__ inline void interpolate(const T* __restrict__ s_tab, const T (&ub)[(NDOF + 3) / 4], int g, int c16,
-                                   typename Mfma<T>::acc_t (&acc)[MT]) {
+// Layout of one 16-cell tile in the matrix-core registers.  Quadrature point
+// p is handled by lane group p % 4 (as its k-th point, k = p / 4); item
+// s = C k + c of a lane group is component c of its k-th point (components
+// 0..2 are the reference gradient, component 3 the value when C = 4) and
+// sits in accumulator element s % 4 of M-tile s / 4.  Every lane therefore
+// owns whole points: the point operator runs in registers, and item s of all
+// four lane groups together is exactly the B operand of K-step s of the
+// integration product.  With C = 3 (no value needed) the 24-point rule fills
+// 5 M-tiles instead of 6.
+//
+// The basis table in LDS is [4 KP points][C][NDOF + 1] (rows beyond the rule
+// are zero).  The integration runs the first 16 DoFs on the matrix cores; the
+// remaining NDOF - 16 DoFs (4 at p = 3), which would fill a second 16-row
+// tile to a quarter, are integrated on the vector ALUs and summed over the
+// four lane groups with cross-lane shuffles (the same fixed order in every
+// lane, so the result is identical in all of them).
+template <typename T, int NDOF, int NQ, int C>
+struct Tile {
   using M = Mfma<T>;
-  constexpr int NDP = NDOF + 1;
-  constexpr int KS = (NDOF + 3) / 4;
-  const int arow = 4 * M::row_g(c16) + M::row_r(c16);  // (point offset, component) of A row c16
-#pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    acc[t] = typename M::acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int col = 4 * s + g;
-      T a = (NDOF % 4 == 0 || col < NDOF) ? s_tab[(16 * t + arow) * NDP + col] : T(0);
-      acc[t] = M::mma(a, ub[s], acc[t]);
-    }
-  }
-}
+  typedef typename M::acc_t acc_t;
+  static constexpr int KP = (NQ + 3) / 4;
+  static constexpr int NS = C * KP;
+  static constexpr int MT = (NS + 3) / 4;
+  static constexpr int KS = (NDOF + 3) / 4;
+  static constexpr int NDP = NDOF + 1;
+  static constexpr int NPT = 4 * KP;
+  static constexpr int NMF = NDOF < 16 ? NDOF : 16;
+  static constexpr int NVA = NDOF - NMF;
+  static constexpr int TAB = NPT * C * NDP;
 
-// V[j, cell] = sum_(t, r) tab[(point 4t+g, comp r), j] T[t][r] for the dof tiles.
-template <typename T, int NDOF, int MT>
-__device__ inline void integrate(const T* __restrict__ s_tab, const typename Mfma<T>::acc_t (&tv)[MT], bool with_value,
-                                 int g, int c16, typename Mfma<T>::acc_t (&v)[(NDOF + 15) / 16]) {
-  using M = Mfma<T>;
-  constexpr int NDP = NDOF + 1;
-  constexpr int DT = (NDOF + 15) / 16;
-#pragma unroll
-  for (int m = 0; m < DT; ++m) {
-    v[m] = typename M::acc_t{0, 0, 0, 0};
-    const int col = 16 * m + c16;
+  // acc[t] = rows (items) of M-tile t for the lane's cell column.
+  __device__ static inline void interpolate(const T* __restrict__ s_tab, const T (&ub)[KS], int g, int c16,
+                                            acc_t (&acc)[MT]) {
+    const int gi = M::row_g(c16), ri = M::row_r(c16);
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
+      const int s = 4 * t + ri;
+      const bool ok = s < NS;
+      const int base = ((gi + 4 * (s / C)) * C + s % C) * NDP;
+      acc[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (r == 3 && !with_value) continue;
-        T a = (col < NDOF) ? s_tab[((4 * t + g) * 4 + r) * NDP + col] : T(0);
-        v[m] = M::mma(a, tv[t][r], v[m]);
+      for (int ks = 0; ks < KS; ++ks) {
+        const int col = 4 * ks + g;
+        const T a = (ok && (NDOF % 4 == 0 || col < NDOF)) ? s_tab[base + col] : T(0);
+        acc[t] = M::mma(a, ub[ks], acc[t]);
       }
     }
   }
-}
+
+  // v: DoFs 0..NMF-1 (element r of lane group g is DoF row(g, r));
+  // vv: DoFs 16..NDOF-1, identical in all lanes of a cell column.
+  __device__ static inline void integrate(const T* __restrict__ s_tab, const acc_t (&acc)[MT], int g, int c16,
+                                          acc_t& v, T (&vv)[NVA > 0 ? NVA : 1]) {
+    v = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const T a = (NMF == 16 || c16 < NMF) ? s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + c16] : T(0);
+      v = M::mma(a, acc[s / 4][s % 4], v);
+    }
+    if (NVA > 0) {
+      T part[NVA > 0 ? NVA : 1];
+#pragma unroll
+      for (int jj = 0; jj < NVA; ++jj) part[jj] = T(0);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const T x = acc[s / 4][s % 4];
+        const T* e = s_tab + ((g + 4 * (s / C)) * C + s % C) * NDP + 16;
+#pragma unroll
+        for (int jj = 0; jj < NVA; ++jj) part[jj] += e[jj] * x;
+      }
+#pragma unroll
+      for (int jj = 0; jj < NVA; ++jj) {
+        T y = part[jj] + __shfl_xor(part[jj], 16);
+        vv[jj] = y + __shfl_xor(y, 32);
+      }
+    }
+  }
+};
 
 // Block range of this workgroup: the blocks are split into 8 contiguous
 // ranges, one per XCD (workgroups are dispatched round-robin over the XCDs),
@@ -114,181 +149,301 @@ __device__ inline void xcd_range(int n, int& first, int& last, int& stride) {
   first = lo + slot;
 }
 
+// Entries staged (or reduced) per thread between two waits for memory.
+constexpr int kStageUnroll = 4;
+
+// Workgroups of a persistent launch: as many as are resident at once on the
+// device (occupancy from the kernel's registers and LDS), a multiple of the 8
+// XCDs, and no more than there is work.
+static int persistent_grid(const void* kern, size_t lds, int work) {
+  int dev = 0, cus = 256, per_cu = 1;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int grid = std::min(work, cus * per_cu);
+  return std::max(8, ((grid + 7) / 8) * 8);
+}
+
 // ---------------------------------------------------------------------------
 // continuous Galerkin: one workgroup pass per block of kBlockCells cells
 //
 // 1. stage the block's DoF values in LDS (private DoFs are a contiguous range
-//    of the global vector; constrained DoFs read as zero: masked gather),
+//    of the global vector; constrained DoFs read as zero: masked gather) and
+//    the block's local DoF indices of every (cell, node),
 // 2. each wave gathers the B operands of its tiles from LDS,
-// 3. interpolate, apply D, integrate (matrix cores), write the 16 x NDOF local
-//    results to LDS slots grouped by block DoF,
+// 3. interpolate, apply D, integrate, write the 16 x NDOF local results to
+//    LDS slots grouped by block DoF,
 // 4. sum every block DoF's slots in a fixed order; private DoFs are stored,
 //    shared DoFs become partial sums that cg_combine adds in block order.
 // Every sum has a fixed order, so the result is bitwise reproducible.
 
-template <typename T, int NDOF, int MT, int MODE>
-__global__ void __launch_bounds__(kThreads) cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin,
-                                                      const T* __restrict__ kappa, T* __restrict__ out,
-                                                      T* __restrict__ dk) {
+// Sum the slots of every block DoF (fixed order) and store them.
+template <typename T>
+__device__ inline void cg_reduce(const CGDev& d, const T* __restrict__ s_slot, int nbd, int npriv, int ps, int oo,
+                                 int po, T* __restrict__ out) {
+  T* partials = static_cast<T*>(d.partials);
+  const int nother = nbd - npriv;
+  for (int k0 = 0; k0 < nbd; k0 += kStageUnroll * kThreads) {
+    int p0[kStageUnroll], p1[kStageUnroll], dst[kStageUnroll];
+#pragma unroll
+    for (int i = 0; i < kStageUnroll; ++i) {
+      const int k = k0 + i * kThreads + threadIdx.x;
+      const bool in = k < nbd;
+      const int kc = min(k, nbd);
+      const int a = d.slot_ptr[po + kc], bnd = d.slot_ptr[po + min(kc + 1, nbd)];
+      const int ps_ = d.other_pslot[oo + min(max(k - npriv, 0), max(nother - 1, 0))];
+      p0[i] = in ? a : 0;
+      p1[i] = in ? bnd : 0;
+      dst[i] = !in ? -1 : (k < npriv ? -2 : ps_);
+    }
+#pragma unroll
+    for (int i = 0; i < kStageUnroll; ++i) {
+      const int k = k0 + i * kThreads + threadIdx.x;
+      T s = 0;
+      for (int p = p0[i]; p < p1[i]; ++p) s += s_slot[p];
+      if (dst[i] == -2)
+        out[ps + k] = s;
+      else if (dst[i] >= 0)
+        partials[dst[i]] = s;
+    }
+  }
+}
+
+template <typename T, int NDOF, int NQ, int C, int MODE>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* __restrict__ kappa,
+          T* __restrict__ out, T* __restrict__ dk) {
+  using TL = Tile<T, NDOF, NQ, C>;
   using M = Mfma<T>;
   typedef typename M::acc_t acc_t;
-  constexpr int NDP = NDOF + 1;
-  constexpr int NROW = MT * 16;
-  constexpr int KS = (NDOF + 3) / 4;
-  constexpr int DT = (NDOF + 15) / 16;
+  constexpr int KS = TL::KS, KP = TL::KP, MT = TL::MT;
   constexpr bool BWD = MODE == MODE_BACKWARD;
-  constexpr bool MF = MODE == MODE_APPLY || MODE == MODE_BACKWARD;
   extern __shared__ __align__(16) unsigned char smem[];
+  // LDS: table | weights | block slots | staged DoF values | local indices
   T* s_tab = reinterpret_cast<T*>(smem);
-  T* s_buf = s_tab + NROW * NDP;
-  const T* tab = static_cast<const T*>(d.tab);
-  for (int i = threadIdx.x; i < NROW * NDP; i += kThreads) s_tab[i] = tab[i];
+  T* s_qw = s_tab + TL::TAB;
+  T* s_slot = s_qw + TL::NPT;
+  T* s_u = s_slot + kBlockCells * NDOF;
+  uint16_t* s_lidx = reinterpret_cast<uint16_t*>(s_u + (BWD ? 2 : 1) * d.nbd_max);
+  {
+    const T* tab = static_cast<const T*>(d.tab);  // global layout [NPT][4][NDP]
+    for (int i = threadIdx.x; i < TL::TAB; i += kThreads) {
+      const int col = i % TL::NDP, c = (i / TL::NDP) % C, p = i / (TL::NDP * C);
+      s_tab[i] = tab[(p * 4 + c) * TL::NDP + col];
+    }
+    for (int i = threadIdx.x; i < TL::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const int ncp = d.ncp, nc = d.n_cell;
   const T* geo = static_cast<const T*>(d.geo);
-  const T* qw = static_cast<const T*>(d.qw);
-  T* partials = static_cast<T*>(d.partials);
-  const bool has_mass = d.sigma != 0.0;
   const T sigma = (T)d.sigma;
   const bool write_out = out != nullptr;
-  T wq[MT];
+  int first, last, stride;
+  xcd_range(d.n_blocks, first, last, stride);
+  for (int b = first; b < last; b += stride) {
+    const int nbd = d.blk_nbd[b], npriv = d.blk_npriv[b], ps = d.blk_priv_start[b];
+    const int oo = d.blk_other_off[b], po = d.blk_ptr_off[b];
+    __syncthreads();  // previous block's slots, staged values and indices are consumed
+    {
+      // block-local indices: [NDOF][kBlockCells] uint16, copied as 32-bit words
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(d.lidx);
+      uint32_t* dstw = reinterpret_cast<uint32_t*>(s_lidx);
+      constexpr int W = NDOF * kBlockCells / 2;
+      uint32_t wv[(W + kThreads - 1) / kThreads];
 #pragma unroll
-  for (int t = 0; t < MT; ++t) wq[t] = qw[4 * t + g];
+      for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
+        const int w = i * kThreads + threadIdx.x;
+        const int j = (2 * w) / kBlockCells, cl = (2 * w) % kBlockCells;
+        wv[i] = w < W ? src[((long)j * ncp + (long)b * kBlockCells + cl) / 2] : 0u;
+      }
+      // DoF values: all index loads first, then all value loads (clamped
+      // indices keep every load in bounds, so no load needs a branch; the
+      // other-DoF lists carry one padding entry for blocks without any)
+      const int nother = nbd - npriv;
+      for (int k0 = 0; k0 < nbd; k0 += kStageUnroll * kThreads) {
+        int gi[kStageUnroll];
+        bool ok[kStageUnroll];
+#pragma unroll
+        for (int i = 0; i < kStageUnroll; ++i) {
+          const int k = k0 + i * kThreads + threadIdx.x;
+          const int oi = min(max(k - npriv, 0), max(nother - 1, 0));
+          const int og = d.other_gid[oo + oi];
+          gi[i] = (k < npriv) ? ps + k : og;
+          ok[i] = k < nbd && (k < npriv || og < d.n_free);
+        }
+        T uv[kStageUnroll], gv[kStageUnroll];
+#pragma unroll
+        for (int i = 0; i < kStageUnroll; ++i) {
+          const int src_i = ok[i] ? gi[i] : 0;
+          uv[i] = u[src_i];
+          if (BWD) gv[i] = gin[src_i];
+          uv[i] = ok[i] ? uv[i] : T(0);
+          if (BWD) gv[i] = ok[i] ? gv[i] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < kStageUnroll; ++i) {
+          const int k = k0 + i * kThreads + threadIdx.x;
+          if (k < nbd) {
+            s_u[k] = uv[i];
+            if (BWD) s_u[d.nbd_max + k] = gv[i];
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
+        const int w = i * kThreads + threadIdx.x;
+        if (w < W) dstw[w] = wv[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int tt = 0; tt < kTilesPerWave; ++tt) {
+      const int cl = (wave + tt * kWaves) * kTile + c16;
+      const int cell = b * kBlockCells + cl;
+      const bool valid = cell < nc;
+      const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
+      const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
+      const T adet = (C == 4) ? geo[6 * ncp + cell] : T(0);
+      // coefficient at this lane's points, loaded from a clamped (always
+      // valid) address and masked afterwards
+      T kq[KP];
+      if (kappa) {
+        const int cc = valid ? cell : nc - 1;
+#pragma unroll
+        for (int k = 0; k < KP; ++k) {
+          const int q = g + 4 * k;
+          kq[k] = kappa[(long)(q < NQ ? q : NQ - 1) * nc + cc];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < KP; ++k) kq[k] = T(1);
+      }
+      uint16_t pv[4 + TL::NVA];
+      if (write_out) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pv[r] = d.pos[M::row(g, r) * ncp + cell];
+        if (TL::NVA > 0) pv[4] = d.pos[(16 + min(g, TL::NVA - 1)) * ncp + cell];
+      }
+      T ub[KS];
+      T gb[BWD ? KS : 1];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int j = 4 * ks + g;
+        const int l = (NDOF % 4 == 0 || j < NDOF) ? s_lidx[j * kBlockCells + cl] : 0;
+        ub[ks] = (NDOF % 4 == 0 || j < NDOF) ? s_u[l] : T(0);
+        if (BWD) gb[BWD ? ks : 0] = (NDOF % 4 == 0 || j < NDOF) ? s_u[d.nbd_max + l] : T(0);
+      }
+      acc_t acc[MT];
+      TL::interpolate(s_tab, ub, g, c16, acc);
+      acc_t accg[BWD ? MT : 1];
+      if (BWD) {
+        T gtmp[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) gtmp[ks] = gb[BWD ? ks : 0];
+        acc_t tmp[MT];
+        TL::interpolate(s_tab, gtmp, g, c16, tmp);
+#pragma unroll
+        for (int t = 0; t < MT; ++t) accg[BWD ? t : 0] = tmp[t];
+      }
+      // point operator D in registers: item s = C k + c at acc[s / 4][s % 4]
+#pragma unroll
+      for (int k = 0; k < KP; ++k) {
+        const int q = g + 4 * k;
+        const T w = s_qw[q];
+        const bool qok = valid && q < NQ;
+        const T s = qok ? kq[k] * w : T(0);
+        const int i0 = C * k;
+        T x, y, z, val = T(0);
+        if (BWD) {
+          const T ux = acc[(i0) / 4][(i0) % 4], uy = acc[(i0 + 1) / 4][(i0 + 1) % 4];
+          const T uz = acc[(i0 + 2) / 4][(i0 + 2) % 4];
+          x = accg[BWD ? (i0) / 4 : 0][(i0) % 4];
+          y = accg[BWD ? (i0 + 1) / 4 : 0][(i0 + 1) % 4];
+          z = accg[BWD ? (i0 + 2) / 4 : 0][(i0 + 2) % 4];
+          if constexpr (C == 4) val = accg[BWD ? (i0 + 3) / 4 : 0][(i0 + 3) % 4];
+          // dkappa = w_q grad_ref(u)^T G grad_ref(g)  (G already holds |det J|)
+          const T dkv = w * (ux * (G0 * x + G1 * y + G2 * z) + uy * (G1 * x + G3 * y + G4 * z) +
+                             uz * (G2 * x + G4 * y + G5 * z));
+          if (dk && qok) dk[(long)q * nc + cell] = dkv;
+        } else {
+          x = acc[(i0) / 4][(i0) % 4];
+          y = acc[(i0 + 1) / 4][(i0 + 1) % 4];
+          z = acc[(i0 + 2) / 4][(i0 + 2) % 4];
+          if constexpr (C == 4) val = acc[(i0 + 3) / 4][(i0 + 3) % 4];
+        }
+        acc[(i0) / 4][(i0) % 4] = s * (G0 * x + G1 * y + G2 * z);
+        acc[(i0 + 1) / 4][(i0 + 1) % 4] = s * (G1 * x + G3 * y + G4 * z);
+        acc[(i0 + 2) / 4][(i0 + 2) % 4] = s * (G2 * x + G4 * y + G5 * z);
+        if constexpr (C == 4) acc[(i0 + 3) / 4][(i0 + 3) % 4] = qok ? sigma * w * adet * val : T(0);
+      }
+      if (write_out) {
+        acc_t v;
+        T vv[TL::NVA > 0 ? TL::NVA : 1];
+        TL::integrate(s_tab, acc, g, c16, v, vv);
+        if (valid) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (TL::NMF == 16 || M::row(g, r) < TL::NMF) s_slot[pv[r]] = v[r];
+          if (TL::NVA > 0 && g < TL::NVA) {
+            T mine = vv[0];
+#pragma unroll
+            for (int jj = 1; jj < (TL::NVA > 0 ? TL::NVA : 1); ++jj) mine = (g == jj) ? vv[jj] : mine;
+            s_slot[pv[4]] = mine;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (write_out) cg_reduce<T>(d, s_slot, nbd, npriv, ps, oo, po, out);
+  }
+}
+
+// Diagonal and load vector (setup-time work, vector ALUs): one (cell, local
+// node) pair per thread, same slots and fixed-order block reduction.
+template <typename T, int NDOF, int NQ, int MODE>
+__global__ void __launch_bounds__(kThreads) cg_vec_kernel(CGDev d, const T* __restrict__ kappa, T* __restrict__ out) {
+  constexpr int NDP = NDOF + 1;
+  constexpr int NPT = 4 * ((NQ + 3) / 4);
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s_tab = reinterpret_cast<T*>(smem);  // [NPT][4][NDP]
+  T* s_slot = s_tab + NPT * 4 * NDP;
+  const T* tab = static_cast<const T*>(d.tab);
+  for (int i = threadIdx.x; i < NPT * 4 * NDP; i += kThreads) s_tab[i] = tab[i];
+  const int ncp = d.ncp, nc = d.n_cell;
+  const T* geo = static_cast<const T*>(d.geo);
+  const T* qw = static_cast<const T*>(d.qw);
+  const bool has_mass = d.sigma != 0.0;
+  const T sigma = (T)d.sigma;
   int first, last, stride;
   xcd_range(d.n_blocks, first, last, stride);
   for (int b = first; b < last; b += stride) {
     __syncthreads();
-    const int nbd = d.blk_nbd[b], npriv = d.blk_npriv[b], ps = d.blk_priv_start[b];
-    const int oo = d.blk_other_off[b], po = d.blk_ptr_off[b];
-    if (MF) {
-      for (int k = threadIdx.x; k < nbd; k += kThreads) {
-        int gi;
-        bool ok = true;
-        if (k < npriv) {
-          gi = ps + k;
+    for (int idx = threadIdx.x; idx < kBlockCells * NDOF; idx += kThreads) {
+      const int cl = idx % kBlockCells, j = idx / kBlockCells;
+      const int cell = b * kBlockCells + cl;
+      if (cell >= nc) continue;
+      const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
+      const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
+      const T adet = geo[6 * ncp + cell];
+      T acc = 0;
+      for (int q = 0; q < NQ; ++q) {
+        const T w = qw[q];
+        const T c = kappa ? kappa[(long)q * nc + cell] : T(1);
+        const T x = s_tab[(q * 4 + 0) * NDP + j], y = s_tab[(q * 4 + 1) * NDP + j];
+        const T z = s_tab[(q * 4 + 2) * NDP + j], val = s_tab[(q * 4 + 3) * NDP + j];
+        if (MODE == MODE_DIAG) {
+          acc += c * w * (G0 * x * x + G3 * y * y + G5 * z * z + T(2) * (G1 * x * y + G2 * x * z + G4 * y * z));
+          if (has_mass) acc += sigma * w * adet * val * val;
         } else {
-          gi = d.other_gid[oo + k - npriv];
-          ok = gi < d.n_free;
+          acc += w * adet * c * val;
         }
-        s_buf[k] = ok ? u[gi] : T(0);
-        if (BWD) s_buf[nbd + k] = ok ? gin[gi] : T(0);
       }
+      s_slot[d.pos[j * ncp + cell]] = acc;
     }
     __syncthreads();
-    T ub[kTilesPerWave][KS];
-    T gb[kTilesPerWave][BWD ? KS : 1];
-    if (MF) {
-#pragma unroll
-      for (int tt = 0; tt < kTilesPerWave; ++tt) {
-        const int cell = b * kBlockCells + (wave + tt * kWaves) * kTile + c16;
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          const int j = 4 * s + g;
-          const int l = (j < NDOF) ? d.lidx[j * ncp + cell] : 0;
-          ub[tt][s] = (j < NDOF) ? s_buf[l] : T(0);
-          if (BWD) gb[tt][s] = (j < NDOF) ? s_buf[nbd + l] : T(0);
-        }
-      }
-    }
-    __syncthreads();
-    if (MF) {
-#pragma unroll
-      for (int tt = 0; tt < kTilesPerWave; ++tt) {
-        const int cell = b * kBlockCells + (wave + tt * kWaves) * kTile + c16;
-        const bool valid = cell < nc;
-        const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
-        const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
-        const T adet = geo[6 * ncp + cell];
-        acc_t acc[MT];
-        interpolate<T, NDOF, MT>(s_tab, ub[tt], g, c16, acc);
-        acc_t accg[BWD ? MT : 1];
-        if (BWD) {
-          T gtmp[KS];
-#pragma unroll
-          for (int s = 0; s < KS; ++s) gtmp[s] = gb[tt][BWD ? s : 0];
-          acc_t tmp[MT];
-          interpolate<T, NDOF, MT>(s_tab, gtmp, g, c16, tmp);
-#pragma unroll
-          for (int t = 0; t < MT; ++t) accg[BWD ? t : 0] = tmp[t];
-        }
-        acc_t tv[MT];
-#pragma unroll
-        for (int t = 0; t < MT; ++t) {
-          const int q = 4 * t + g;
-          const bool qok = valid && q < d.nq;
-          const T kap = qok ? (kappa ? kappa[(long)q * nc + cell] : T(1)) : T(0);
-          const T s = kap * wq[t];
-          if (BWD) {
-            // dkappa = w_q grad_ref(u)^T G grad_ref(g)  (G already holds |det J|)
-            const T ux = acc[t][0], uy = acc[t][1], uz = acc[t][2];
-            const acc_t& gg = accg[BWD ? t : 0];
-            const T gx = gg[0], gy = gg[1], gz = gg[2];
-            const T dkv = wq[t] * (ux * (G0 * gx + G1 * gy + G2 * gz) + uy * (G1 * gx + G3 * gy + G4 * gz) +
-                                   uz * (G2 * gx + G4 * gy + G5 * gz));
-            if (dk && qok) dk[(long)q * nc + cell] = dkv;
-          }
-          const acc_t& src = BWD ? accg[BWD ? t : 0] : acc[t];
-          const T x = src[0], y = src[1], z = src[2];
-          tv[t][0] = s * (G0 * x + G1 * y + G2 * z);
-          tv[t][1] = s * (G1 * x + G3 * y + G4 * z);
-          tv[t][2] = s * (G2 * x + G4 * y + G5 * z);
-          tv[t][3] = (has_mass && q < d.nq) ? sigma * wq[t] * adet * src[3] : T(0);
-        }
-        if (write_out) {
-          acc_t v[DT];
-          integrate<T, NDOF, MT>(s_tab, tv, has_mass, g, c16, v);
-          if (valid) {
-#pragma unroll
-            for (int m = 0; m < DT; ++m)
-#pragma unroll
-              for (int r = 0; r < 4; ++r) {
-                const int j = 16 * m + M::row(g, r);
-                if (j < NDOF) s_buf[d.pos[j * ncp + cell]] = v[m][r];
-              }
-          }
-        }
-      }
-    } else {
-      // diagonal / load vector: one (cell, local node) pair per thread
-      for (int idx = threadIdx.x; idx < kBlockCells * NDOF; idx += kThreads) {
-        const int cl = idx % kBlockCells, j = idx / kBlockCells;
-        const int cell = b * kBlockCells + cl;
-        if (cell >= nc) continue;
-        const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
-        const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
-        const T adet = geo[6 * ncp + cell];
-        T acc = 0;
-        for (int q = 0; q < d.nq; ++q) {
-          const T w = qw[q];
-          const T c = kappa ? kappa[(long)q * nc + cell] : T(1);
-          const T x = s_tab[(q * 4 + 0) * NDP + j], y = s_tab[(q * 4 + 1) * NDP + j];
-          const T z = s_tab[(q * 4 + 2) * NDP + j], val = s_tab[(q * 4 + 3) * NDP + j];
-          if (MODE == MODE_DIAG) {
-            acc += c * w *
-                   (G0 * x * x + G3 * y * y + G5 * z * z + T(2) * (G1 * x * y + G2 * x * z + G4 * y * z));
-            if (has_mass) acc += sigma * w * adet * val * val;
-          } else {
-            acc += w * adet * c * val;
-          }
-        }
-        s_buf[d.pos[j * ncp + cell]] = acc;
-      }
-    }
-    __syncthreads();
-    if (write_out) {
-      for (int k = threadIdx.x; k < nbd; k += kThreads) {
-        const int p0 = d.slot_ptr[po + k], p1 = d.slot_ptr[po + k + 1];
-        T s = 0;
-        for (int p = p0; p < p1; ++p) s += s_buf[p];
-        if (k < npriv) {
-          out[ps + k] = s;
-        } else {
-          const int slot = d.other_pslot[oo + k - npriv];
-          if (slot >= 0) partials[slot] = s;
-        }
-      }
-    }
+    cg_reduce<T>(d, s_slot, d.blk_nbd[b], d.blk_npriv[b], d.blk_priv_start[b], d.blk_other_off[b],
+                 d.blk_ptr_off[b], out);
   }
 }
 
@@ -312,63 +467,84 @@ __global__ void __launch_bounds__(256) cg_combine(CGDev d, const T* __restrict__
   }
 }
 
-template <typename T, int NDOF, int MT, int MODE>
-hipError_t launch_cg_t(const CGDev& d, const void* u, const void* g, const void* kappa, void* out, void* dk,
-                       hipStream_t s, hipEvent_t* ev) {
-  constexpr int NROW = MT * 16;
-  constexpr int NDP = NDOF + 1;
-  const int bufn = std::max(kBlockCells * NDOF, (MODE == MODE_BACKWARD ? 2 : 1) * d.nbd_max);
-  const size_t lds = (size_t)(NROW * NDP + bufn) * sizeof(T);
+template <typename T, int MODE>
+hipError_t launch_combine(const CGDev& d, const void* src, void* out, hipStream_t s) {
+  const int nfix = d.n_shared + (d.n_dofs - d.n_free);
+  if (nfix > 0) hipLaunchKernelGGL((cg_combine<T, MODE>), dim3((nfix + 255) / 256), dim3(256), 0, s, d, (const T*)src,
+                                   (T*)out);
+  return hipGetLastError();
+}
+
+template <typename T, int NDOF, int NQ, int C, int MODE>
+hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void* kappa, void* out, void* dk,
+                        hipStream_t s, hipEvent_t* ev) {
+  using TL = Tile<T, NDOF, NQ, C>;
+  const int ustage = (MODE == MODE_BACKWARD ? 2 : 1) * d.nbd_max;
+  const size_t lds = (size_t)(TL::TAB + TL::NPT + kBlockCells * NDOF + ustage) * sizeof(T) +
+                     (size_t)NDOF * kBlockCells * sizeof(uint16_t);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  const int per_cu = lds <= 80 * 1024 ? 2 : 1;
-  int grid = std::min(d.n_blocks, 256 * per_cu);
-  grid = ((grid + 7) / 8) * 8;
-  auto kern = cg_kernel<T, NDOF, MT, MODE>;
+  auto kern = cg_kernel<T, NDOF, NQ, C, MODE>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)g, (const T*)kappa, (T*)out,
                      (T*)dk);
   e = hipGetLastError();
   if (ev) (void)hipEventRecord(ev[1], s);
   if (e != hipSuccess || out == nullptr) return e;
-  const int nfix = d.n_shared + (d.n_dofs - d.n_free);
-  if (nfix > 0) {
-    const T* src = (const T*)(MODE == MODE_BACKWARD ? g : u);
-    hipLaunchKernelGGL((cg_combine<T, MODE>), dim3((nfix + 255) / 256), dim3(256), 0, s, d, src, (T*)out);
-    e = hipGetLastError();
-  }
-  return e;
+  return launch_combine<T, MODE>(d, MODE == MODE_BACKWARD ? g : u, out, s);
 }
 
-template <typename T, int NDOF, int MT>
+template <typename T, int NDOF, int NQ, int MODE>
+hipError_t launch_cg_vec(const CGDev& d, const void* kappa, void* out, hipStream_t s, hipEvent_t* ev) {
+  constexpr int NPT = 4 * ((NQ + 3) / 4);
+  const size_t lds = (size_t)(NPT * 4 * (NDOF + 1) + kBlockCells * NDOF) * sizeof(T);
+  auto kern = cg_vec_kernel<T, NDOF, NQ, MODE>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)kappa, (T*)out);
+  e = hipGetLastError();
+  if (ev) (void)hipEventRecord(ev[1], s);
+  if (e != hipSuccess) return e;
+  return launch_combine<T, MODE>(d, nullptr, out, s);
+}
+
+template <typename T, int NDOF, int NQ>
 hipError_t launch_cg_mode(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
                           void* dk, hipStream_t s, hipEvent_t* ev) {
+  const bool mass = d.sigma != 0.0;
   switch (mode) {
-    case MODE_APPLY: return launch_cg_t<T, NDOF, MT, MODE_APPLY>(d, u, g, kappa, out, dk, s, ev);
-    case MODE_BACKWARD: return launch_cg_t<T, NDOF, MT, MODE_BACKWARD>(d, u, g, kappa, out, dk, s, ev);
-    case MODE_DIAG: return launch_cg_t<T, NDOF, MT, MODE_DIAG>(d, u, g, kappa, out, dk, s, ev);
-    default: return launch_cg_t<T, NDOF, MT, MODE_LOAD>(d, u, g, kappa, out, dk, s, ev);
+    case MODE_APPLY:
+      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_APPLY>(d, u, g, kappa, out, dk, s, ev)
+                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_APPLY>(d, u, g, kappa, out, dk, s, ev);
+    case MODE_BACKWARD:
+      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_BACKWARD>(d, u, g, kappa, out, dk, s, ev)
+                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_BACKWARD>(d, u, g, kappa, out, dk, s, ev);
+    case MODE_DIAG: return launch_cg_vec<T, NDOF, NQ, MODE_DIAG>(d, kappa, out, s, ev);
+    default: return launch_cg_vec<T, NDOF, NQ, MODE_LOAD>(d, kappa, out, s, ev);
   }
 }
 
 template <typename T>
-hipError_t launch_cg_shape(const CGDev& d, int ndof, int mt, int mode, const void* u, const void* g,
+hipError_t launch_cg_shape(const CGDev& d, int ndof, int nq, int mode, const void* u, const void* g,
                            const void* kappa, void* out, void* dk, hipStream_t s, bool* supported, hipEvent_t* ev) {
   *supported = true;
-  if (ndof == 4 && mt == 1) return launch_cg_mode<T, 4, 1>(d, mode, u, g, kappa, out, dk, s, ev);
-  if (ndof == 10 && mt == 1) return launch_cg_mode<T, 10, 1>(d, mode, u, g, kappa, out, dk, s, ev);
-  if (ndof == 10 && mt == 4) return launch_cg_mode<T, 10, 4>(d, mode, u, g, kappa, out, dk, s, ev);
-  if (ndof == 20 && mt == 4) return launch_cg_mode<T, 20, 4>(d, mode, u, g, kappa, out, dk, s, ev);
-  if (ndof == 20 && mt == 6) return launch_cg_mode<T, 20, 6>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 4 && nq == 4) return launch_cg_mode<T, 4, 4>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 10 && nq == 4) return launch_cg_mode<T, 10, 4>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 10 && nq == 14) return launch_cg_mode<T, 10, 14>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 20 && nq == 14) return launch_cg_mode<T, 20, 14>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 20 && nq == 24) return launch_cg_mode<T, 20, 24>(d, mode, u, g, kappa, out, dk, s, ev);
   *supported = false;
   return hipSuccess;
 }
 
-hipError_t launch_cg(const CGDev& d, int prec, int ndof, int mt, int mode, const void* u, const void* g,
+hipError_t launch_cg(const CGDev& d, int prec, int ndof, int nq, int mode, const void* u, const void* g,
                      const void* kappa, void* out, void* dk, hipStream_t s, bool* supported, hipEvent_t* ev) {
-  if (prec == PREC_F64) return launch_cg_shape<double>(d, ndof, mt, mode, u, g, kappa, out, dk, s, supported, ev);
-  if (prec == PREC_F32) return launch_cg_shape<float>(d, ndof, mt, mode, u, g, kappa, out, dk, s, supported, ev);
+  if (prec == PREC_F64) return launch_cg_shape<double>(d, ndof, nq, mode, u, g, kappa, out, dk, s, supported, ev);
+  if (prec == PREC_F32) return launch_cg_shape<float>(d, ndof, nq, mode, u, g, kappa, out, dk, s, supported, ev);
   *supported = false;
   return hipSuccess;
 }
@@ -392,41 +568,39 @@ hipError_t launch_cg(const CGDev& d, int prec, int ndof, int mt, int mode, const
 //   value test:     omega kappa (tau [[u]] - {{d_n u}})
 //   gradient test:  -omega kappa [[u]] / 2 * b_own
 
-template <typename T, int NDOF, int MT, int MTF>
-__global__ void __launch_bounds__(kThreads) dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc,
-                                                      const T* __restrict__ kf, T* __restrict__ v) {
+template <typename T, int NDOF, int NQ, int NQF, int C>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* __restrict__ kf, T* __restrict__ v) {
+  using TC = Tile<T, NDOF, NQ, C>;
+  using TF = Tile<T, NDOF, NQF, 4>;
   using M = Mfma<T>;
   typedef typename M::acc_t acc_t;
-  constexpr int NDP = NDOF + 1;
-  constexpr int NROW = MT * 16;
-  constexpr int NROWF = MTF * 16;
-  constexpr int KS = (NDOF + 3) / 4;
-  constexpr int DT = (NDOF + 15) / 16;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* s_tab = reinterpret_cast<T*>(smem);
-  T* s_ftab = s_tab + NROW * NDP;
-  T* s_out = s_ftab + NROWF * NDP;
+  T* s_tab = reinterpret_cast<T*>(smem);   // [NPT][C][NDP]
+  T* s_ftab = s_tab + TC::TAB;              // [NPTF][4][NDP]
+  T* s_qw = s_ftab + TF::TAB;
+  T* s_fw = s_qw + TC::NPT;
+  T* s_out = s_fw + TF::NPT;                // [kWaves][kTile * NDOF]
   int* s_perm = reinterpret_cast<int*>(s_out + kWaves * kTile * NDOF);
-  const T* tab = static_cast<const T*>(d.tab);
-  const T* ftab = static_cast<const T*>(d.ftab);
-  for (int i = threadIdx.x; i < NROW * NDP; i += kThreads) s_tab[i] = tab[i];
-  for (int i = threadIdx.x; i < NROWF * NDP; i += kThreads) s_ftab[i] = ftab[i];
-  for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
+  {
+    const T* tab = static_cast<const T*>(d.tab);
+    for (int i = threadIdx.x; i < TC::TAB; i += kThreads) {
+      const int col = i % TC::NDP, c = (i / TC::NDP) % C, p = i / (TC::NDP * C);
+      s_tab[i] = tab[(p * 4 + c) * TC::NDP + col];
+    }
+    const T* ftab = static_cast<const T*>(d.ftab);
+    for (int i = threadIdx.x; i < TF::TAB; i += kThreads) s_ftab[i] = ftab[i];
+    for (int i = threadIdx.x; i < TC::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
+    for (int i = threadIdx.x; i < TF::NPT; i += kThreads) s_fw[i] = static_cast<const T*>(d.fw)[i];
+    for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const int ncp = d.ncp, nc = d.n_cell, nf = d.n_face;
   const T* geo = static_cast<const T*>(d.geo);
   const T* fgeo = static_cast<const T*>(d.fgeo);
-  const T* qw = static_cast<const T*>(d.qw);
-  const T* fw = static_cast<const T*>(d.fw);
-  const bool has_mass = d.sigma != 0.0;
   const T sigma = (T)d.sigma;
-  T wq[MT], fwq[MTF];
-#pragma unroll
-  for (int t = 0; t < MT; ++t) wq[t] = qw[4 * t + g];
-#pragma unroll
-  for (int t = 0; t < MTF; ++t) fwq[t] = fw[4 * t + g];
   T* so = s_out + wave * kTile * NDOF;
   // tiles of this wave: contiguous tile ranges per XCD
   const int ntiles = ncp / kTile;
@@ -438,40 +612,53 @@ __global__ void __launch_bounds__(kThreads) dg_kernel(DGDev d, const T* __restri
     const int cell0 = tile * kTile;
     const int cell = cell0 + c16;
     const bool valid = cell < nc;
+    const int cc = valid ? cell : nc - 1;
     // ---- cell term
     {
-      T ub[KS];
+      T ub[TC::KS];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
+      for (int s = 0; s < TC::KS; ++s) {
         const int j = 4 * s + g;
         ub[s] = (valid && j < NDOF) ? u[(long)cell * NDOF + j] : T(0);
       }
       const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
       const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
-      const T adet = geo[6 * ncp + cell];
-      acc_t acc[MT];
-      interpolate<T, NDOF, MT>(s_tab, ub, g, c16, acc);
-      acc_t tv[MT];
+      const T adet = (C == 4) ? geo[6 * ncp + cell] : T(0);
+      T kq[TC::KP];
 #pragma unroll
-      for (int t = 0; t < MT; ++t) {
-        const int q = 4 * t + g;
-        const bool qok = valid && q < d.nq;
-        const T s = (qok ? (kc ? kc[(long)q * nc + cell] : T(1)) : T(0)) * wq[t];
-        const T xg = acc[t][0], yg = acc[t][1], zg = acc[t][2];
-        tv[t][0] = s * (G0 * xg + G1 * yg + G2 * zg);
-        tv[t][1] = s * (G1 * xg + G3 * yg + G4 * zg);
-        tv[t][2] = s * (G2 * xg + G4 * yg + G5 * zg);
-        tv[t][3] = (has_mass && qok) ? sigma * wq[t] * adet * acc[t][3] : T(0);
+      for (int k = 0; k < TC::KP; ++k) {
+        const int q = g + 4 * k;
+        kq[k] = kc ? kc[(long)(q < NQ ? q : NQ - 1) * nc + cc] : T(1);
       }
-      acc_t vv[DT];
-      integrate<T, NDOF, MT>(s_tab, tv, has_mass, g, c16, vv);
+      acc_t acc[TC::MT];
+      TC::interpolate(s_tab, ub, g, c16, acc);
 #pragma unroll
-      for (int m = 0; m < DT; ++m)
+      for (int k = 0; k < TC::KP; ++k) {
+        const int q = g + 4 * k;
+        const bool qok = valid && q < NQ;
+        const T w = s_qw[q];
+        const T s = qok ? kq[k] * w : T(0);
+        const int i0 = C * k;
+        const T xg = acc[i0 / 4][i0 % 4], yg = acc[(i0 + 1) / 4][(i0 + 1) % 4], zg = acc[(i0 + 2) / 4][(i0 + 2) % 4];
+        T val = T(0);
+        if constexpr (C == 4) val = acc[(i0 + 3) / 4][(i0 + 3) % 4];
+        acc[i0 / 4][i0 % 4] = s * (G0 * xg + G1 * yg + G2 * zg);
+        acc[(i0 + 1) / 4][(i0 + 1) % 4] = s * (G1 * xg + G3 * yg + G4 * zg);
+        acc[(i0 + 2) / 4][(i0 + 2) % 4] = s * (G2 * xg + G4 * yg + G5 * zg);
+        if constexpr (C == 4) acc[(i0 + 3) / 4][(i0 + 3) % 4] = qok ? sigma * w * adet * val : T(0);
+      }
+      acc_t vm;
+      T vv[TC::NVA > 0 ? TC::NVA : 1];
+      TC::integrate(s_tab, acc, g, c16, vm, vv);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int j = 16 * m + M::row(g, r);
-          if (j < NDOF) so[c16 * NDOF + j] = vv[m][r];
-        }
+      for (int r = 0; r < 4; ++r)
+        if (TC::NMF == 16 || M::row(g, r) < TC::NMF) so[c16 * NDOF + M::row(g, r)] = vm[r];
+      if (TC::NVA > 0 && g < TC::NVA) {
+        T mine = vv[0];
+#pragma unroll
+        for (int jj = 1; jj < (TC::NVA > 0 ? TC::NVA : 1); ++jj) mine = (g == jj) ? vv[jj] : mine;
+        so[c16 * NDOF + 16 + g] = mine;
+      }
     }
     // ---- face terms
 #pragma unroll 1
@@ -485,48 +672,63 @@ __global__ void __launch_bounds__(kThreads) dg_kernel(DGDev d, const T* __restri
       const bool active = valid && (!boundary || d.dirichlet);
       T bo[3], bn[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        bo[k] = fgeo[((long)k * 4 + f) * ncp + cell];
-        bn[k] = fgeo[((long)(3 + k) * 4 + f) * ncp + cell];
+      for (int q = 0; q < 3; ++q) {
+        bo[q] = fgeo[((long)q * 4 + f) * ncp + cell];
+        bn[q] = fgeo[((long)(3 + q) * 4 + f) * ncp + cell];
       }
       const T om = fgeo[((long)6 * 4 + f) * ncp + cell];
       const T tau = fgeo[((long)7 * 4 + f) * ncp + cell];
-      T um[KS], up[KS];
+      T kfq[TF::KP];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
+      for (int k = 0; k < TF::KP; ++k) {
+        const int q = g + 4 * k;
+        kfq[k] = kf ? kf[(long)(q < NQF ? q : NQF - 1) * nf + fidv] : T(1);
+      }
+      T um[TF::KS], up[TF::KS];
+      const int nbs = boundary ? cc : nbc;
+#pragma unroll
+      for (int s = 0; s < TF::KS; ++s) {
         const int j = 4 * s + g;
-        um[s] = (valid && j < NDOF) ? u[(long)cell * NDOF + s_perm[ro * NDOF + j]] : T(0);
-        up[s] = (!boundary && j < NDOF) ? u[(long)nbc * NDOF + s_perm[rn * NDOF + j]] : T(0);
+        const int jc = j < NDOF ? j : NDOF - 1;
+        const T a = u[(long)cc * NDOF + s_perm[ro * NDOF + jc]];
+        const T bq = u[(long)nbs * NDOF + s_perm[rn * NDOF + jc]];
+        um[s] = (valid && j < NDOF) ? a : T(0);
+        up[s] = (!boundary && j < NDOF) ? bq : T(0);
       }
-      acc_t am[MTF], ap[MTF];
-      interpolate<T, NDOF, MTF>(s_ftab, um, g, c16, am);
-      interpolate<T, NDOF, MTF>(s_ftab, up, g, c16, ap);
-      acc_t tv[MTF];
+      acc_t am[TF::MT], ap[TF::MT];
+      TF::interpolate(s_ftab, um, g, c16, am);
+      TF::interpolate(s_ftab, up, g, c16, ap);
 #pragma unroll
-      for (int t = 0; t < MTF; ++t) {
-        const int q = 4 * t + g;
-        const bool qok = active && q < d.nqf;
-        const T s = (qok ? (kf ? kf[(long)q * nf + fidv] : T(1)) : T(0)) * fwq[t] * om;
-        const T dnm = bo[0] * am[t][0] + bo[1] * am[t][1] + bo[2] * am[t][2];
-        const T dnp = bn[0] * ap[t][0] + bn[1] * ap[t][1] + bn[2] * ap[t][2];
-        const T jump = boundary ? T(2) * am[t][3] : am[t][3] - ap[t][3];
+      for (int k = 0; k < TF::KP; ++k) {
+        const int q = g + 4 * k;
+        const bool qok = active && q < NQF;
+        const T s = qok ? kfq[k] * s_fw[q] * om : T(0);
+        const int i0 = 4 * k;
+        const T dnm = bo[0] * am[i0 / 4][0] + bo[1] * am[i0 / 4][1] + bo[2] * am[i0 / 4][2];
+        const T dnp = bn[0] * ap[i0 / 4][0] + bn[1] * ap[i0 / 4][1] + bn[2] * ap[i0 / 4][2];
+        const T jump = boundary ? T(2) * am[i0 / 4][3] : am[i0 / 4][3] - ap[i0 / 4][3];
         const T avg = boundary ? dnm : T(0.5) * (dnm + dnp);
-        const T cg = T(-0.5) * s * jump;
-        tv[t][0] = cg * bo[0];
-        tv[t][1] = cg * bo[1];
-        tv[t][2] = cg * bo[2];
-        tv[t][3] = s * (tau * jump - avg);
+        const T cgr = T(-0.5) * s * jump;
+        am[i0 / 4][0] = cgr * bo[0];
+        am[i0 / 4][1] = cgr * bo[1];
+        am[i0 / 4][2] = cgr * bo[2];
+        am[i0 / 4][3] = s * (tau * jump - avg);
       }
-      acc_t vf[DT];
-      integrate<T, NDOF, MTF>(s_ftab, tv, true, g, c16, vf);
+      acc_t vf;
+      T vvf[TF::NVA > 0 ? TF::NVA : 1];
+      TF::integrate(s_ftab, am, g, c16, vf, vvf);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
-      for (int m = 0; m < DT; ++m)
+      for (int r = 0; r < 4; ++r) {
+        const int j = M::row(g, r);
+        if (TF::NMF == 16 || j < TF::NMF) so[c16 * NDOF + s_perm[ro * NDOF + j]] += vf[r];
+      }
+      if (TF::NVA > 0 && g < TF::NVA) {
+        T mine = vvf[0];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int j = 16 * m + M::row(g, r);
-          if (j < NDOF) so[c16 * NDOF + s_perm[ro * NDOF + j]] += vf[m][r];
-        }
+        for (int jj = 1; jj < (TF::NVA > 0 ? TF::NVA : 1); ++jj) mine = (g == jj) ? vvf[jj] : mine;
+        so[c16 * NDOF + s_perm[ro * NDOF + 16 + g]] += mine;
+      }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
     // ---- store the tile (contiguous 16 x NDOF block of the DG vector)
@@ -536,17 +738,18 @@ __global__ void __launch_bounds__(kThreads) dg_kernel(DGDev d, const T* __restri
   }
 }
 
-template <typename T, int NDOF, int MT, int MTF>
+template <typename T, int NDOF, int NQ, int NQF, int C>
 hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void* kf, void* v, hipStream_t s,
                        hipEvent_t* ev) {
-  constexpr int NDP = NDOF + 1;
-  const size_t lds = (size_t)((MT + MTF) * 16 * NDP + kWaves * kTile * NDOF) * sizeof(T) + 24 * NDOF * sizeof(int);
+  using TC = Tile<T, NDOF, NQ, C>;
+  using TF = Tile<T, NDOF, NQF, 4>;
+  const size_t lds = (size_t)(TC::TAB + TF::TAB + TC::NPT + TF::NPT + kWaves * kTile * NDOF) * sizeof(T) +
+                     24 * NDOF * sizeof(int);
   const int ntiles = d.ncp / kTile;
-  int grid = std::min((ntiles + kWaves - 1) / kWaves, 256 * 2);
-  grid = ((grid + 7) / 8) * 8;
-  auto kern = dg_kernel<T, NDOF, MT, MTF>;
+  auto kern = dg_kernel<T, NDOF, NQ, NQF, C>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  const int grid = persistent_grid((const void*)kern, lds, (ntiles + kWaves - 1) / kWaves);
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)kc, (const T*)kf, (T*)v);
   e = hipGetLastError();
@@ -555,20 +758,26 @@ hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void
 }
 
 template <typename T>
-hipError_t launch_dg_shape(const DGDev& d, int ndof, int mt, int mtf, const void* u, const void* kc,
-                           const void* kf, void* v, hipStream_t s, bool* supported, hipEvent_t* ev) {
+hipError_t launch_dg_shape(const DGDev& d, int ndof, int nq, int nqf, const void* u, const void* kc, const void* kf,
+                           void* v, hipStream_t s, bool* supported, hipEvent_t* ev) {
   *supported = true;
-  if (ndof == 4 && mt == 1 && mtf == 1) return launch_dg_t<T, 4, 1, 1>(d, u, kc, kf, v, s, ev);
-  if (ndof == 10 && mt == 4 && mtf == 2) return launch_dg_t<T, 10, 4, 2>(d, u, kc, kf, v, s, ev);
-  if (ndof == 20 && mt == 6 && mtf == 3) return launch_dg_t<T, 20, 6, 3>(d, u, kc, kf, v, s, ev);
+  const bool mass = d.sigma != 0.0;
+#define TETMF_DG_CASE(ND, Q, QF)                                                         \
+  if (ndof == ND && nq == Q && nqf == QF)                                                \
+    return mass ? launch_dg_t<T, ND, Q, QF, 4>(d, u, kc, kf, v, s, ev)                   \
+                : launch_dg_t<T, ND, Q, QF, 3>(d, u, kc, kf, v, s, ev);
+  TETMF_DG_CASE(4, 4, 3)
+  TETMF_DG_CASE(10, 14, 6)
+  TETMF_DG_CASE(20, 24, 12)
+#undef TETMF_DG_CASE
   *supported = false;
   return hipSuccess;
 }
 
-hipError_t launch_dg(const DGDev& d, int prec, int ndof, int mt, int mtf, const void* u, const void* kc,
+hipError_t launch_dg(const DGDev& d, int prec, int ndof, int nq, int nqf, const void* u, const void* kc,
                      const void* kf, void* v, hipStream_t s, bool* supported, hipEvent_t* ev) {
-  if (prec == PREC_F64) return launch_dg_shape<double>(d, ndof, mt, mtf, u, kc, kf, v, s, supported, ev);
-  if (prec == PREC_F32) return launch_dg_shape<float>(d, ndof, mt, mtf, u, kc, kf, v, s, supported, ev);
+  if (prec == PREC_F64) return launch_dg_shape<double>(d, ndof, nq, nqf, u, kc, kf, v, s, supported, ev);
+  if (prec == PREC_F32) return launch_dg_shape<float>(d, ndof, nq, nqf, u, kc, kf, v, s, supported, ev);
   *supported = false;
   return hipSuccess;
 }

@@ -723,6 +723,9 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m) {
       }
     }
   }
+  // padding entry: every block's list offset stays a valid index
+  other_gid.push_back(0);
+  other_pslot.push_back(-1);
   std::vector<int32_t> sh_ptr(sh_gid.size() + 1, 0);
   for (size_t s = 0; s < sh_gid.size(); ++s) sh_ptr[s + 1] = sh_ptr[s] + sh_count[s];
   op->n_partials = sh_ptr.back();
@@ -953,12 +956,13 @@ extern "C" int tetmf_op_create(const tetmf_mesh* mesh, const tetmf_op_desc* d, t
     op->mesh_nv = mesh->nv;
     // supported kernel instantiations
     bool ok;
+    // compiled kernel shapes: (DoFs per cell, cell points[, face points])
     if (op->kind == TETMF_CG)
-      ok = (op->ndof == 4 && op->mt == 1) || (op->ndof == 10 && (op->mt == 1 || op->mt == 4)) ||
-           (op->ndof == 20 && (op->mt == 4 || op->mt == 6));
+      ok = (op->ndof == 4 && op->nq == 4) || (op->ndof == 10 && (op->nq == 4 || op->nq == 14)) ||
+           (op->ndof == 20 && (op->nq == 14 || op->nq == 24));
     else
-      ok = (op->ndof == 4 && op->mt == 1 && op->mtf == 1) || (op->ndof == 10 && op->mt == 4 && op->mtf == 2) ||
-           (op->ndof == 20 && op->mt == 6 && op->mtf == 3);
+      ok = (op->ndof == 4 && op->nq == 4 && op->nqf == 3) || (op->ndof == 10 && op->nq == 14 && op->nqf == 6) ||
+           (op->ndof == 20 && op->nq == 24 && op->nqf == 12);
     if (op->kind == TETMF_DG && op->prec == TETMF_BF16IN) ok = false;
     if (!ok)
       return fail(TETMF_ERR_UNSUPPORTED, "tetmf_op_create: no kernel for degree " + std::to_string(op->degree) +
@@ -1039,7 +1043,7 @@ int run_cg(tetmf_op* op, int mode, const void* u, const void* g, const void* kap
            void* stream) {
   DeviceScope ds(op->device);
   bool supported = true;
-  hipError_t e = launch_cg(op->cg, kernel_prec(op), op->ndof, op->mt, mode, u, g, kappa, out, dk,
+  hipError_t e = launch_cg(op->cg, kernel_prec(op), op->ndof, op->nq, mode, u, g, kappa, out, dk,
                            (hipStream_t)stream, &supported, op->next_events());
   if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no kernel instantiation for this operator");
   check_hip(e, "kernel launch");
@@ -1071,7 +1075,7 @@ extern "C" int tetmf_apply(tetmf_op* op, const void* u, const void* kappa_cell, 
     }
     DeviceScope ds(op->device);
     bool supported = true;
-    hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->mt, op->mtf, u, kappa_cell, kappa_face, v,
+    hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, u, kappa_cell, kappa_face, v,
                              (hipStream_t)stream, &supported, op->next_events());
     if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
     check_hip(e, "kernel launch");
