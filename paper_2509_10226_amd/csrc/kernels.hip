@@ -86,6 +86,29 @@ struct Tile {
   static constexpr int NMF = NDOF < 16 ? NDOF : 16;
   static constexpr int NVA = NDOF - NMF;
   static constexpr int TAB = NPT * C * NDP;
+  // B operand of the interpolation: lane group g supplies DoFs bdof(g, i), i < NB
+  static constexpr int NB = KS;
+  __device__ static constexpr int bdof(int g, int i) { return 4 * i + g; }
+  // LDS bytes of the engine's tables (a multiple of 16)
+  static constexpr int LDS_BYTES = (TAB * (int)sizeof(T) + 15) / 16 * 16;
+
+  // Tables from the global [NPT][4][NDOF + 1] layout into LDS.
+  __device__ static inline void setup(unsigned char* lds, const T* __restrict__ gtab, int tid, int nt) {
+    T* s_tab = reinterpret_cast<T*>(lds);
+    for (int i = tid; i < TAB; i += nt) {
+      const int col = i % NDP, c = (i / NDP) % C, p = i / (NDP * C);
+      s_tab[i] = gtab[(p * 4 + c) * NDP + col];
+    }
+  }
+
+  __device__ static inline void interpolate(const unsigned char* lds, const T (&ub)[KS], int g, int c16,
+                                            acc_t (&acc)[MT]) {
+    interpolate(reinterpret_cast<const T*>(lds), ub, g, c16, acc);
+  }
+  __device__ static inline void integrate(const unsigned char* lds, const acc_t (&acc)[MT], int g, int c16, acc_t& v,
+                                          T (&vv)[NDOF - (NDOF < 16 ? NDOF : 16) > 0 ? NDOF - (NDOF < 16 ? NDOF : 16) : 1]) {
+    integrate(reinterpret_cast<const T*>(lds), acc, g, c16, v, vv);
+  }
 
   // acc[t] = rows (items) of M-tile t for the lane's cell column.
   __device__ static inline void interpolate(const T* __restrict__ s_tab, const T (&ub)[KS], int g, int c16,
@@ -134,6 +157,112 @@ struct Tile {
       }
     }
   }
+};
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// BF16-operand engine: the same item layout as Tile<float> (the f32 16x16
+// accumulator layout), but both products run as 16x16x32 BF16 matrix-core
+// operations with FP32 accumulation.  Interpolation: one K-step covers all
+// DoFs (lane group g supplies DoFs 8g..8g+7); integration: K-step ks takes
+// items 8ks..8ks+7 of every lane group.  The operands are rounded to BF16
+// (the table once at set-up, the DoF values and point values when they enter
+// a product); the point operator, accumulation and the vector-ALU tail for
+// DoFs 16.. run in FP32.  Tables in LDS: the FP32 table of Tile<float> (for
+// the tail), then the BF16 interpolation A operands [MT][16][32] and the
+// BF16 integration A operands [KSI][16][32], each lane reading 16 bytes.
+template <int NDOF, int NQ, int C>
+struct TileBF {
+  using F = Tile<float, NDOF, NQ, C>;
+  using M = Mfma<float>;
+  typedef typename M::acc_t acc_t;
+  static constexpr int KP = F::KP, NS = F::NS, MT = F::MT, NDP = F::NDP, NPT = F::NPT;
+  static constexpr int NMF = F::NMF, NVA = F::NVA;
+  static constexpr int KSI = (NS + 7) / 8;
+  static constexpr int NB = 8;
+  __device__ static constexpr int bdof(int g, int i) { return 8 * g + i; }
+  static constexpr int F32_BYTES = F::LDS_BYTES;
+  static constexpr int A_BYTES = MT * 16 * 32 * 2;
+  static constexpr int B_BYTES = KSI * 16 * 32 * 2;
+  static constexpr int LDS_BYTES = F32_BYTES + A_BYTES + B_BYTES;
+  static_assert(NDOF <= 32, "one BF16 K-step covers at most 32 DoFs");
+
+  __device__ static inline void setup(unsigned char* lds, const float* __restrict__ gtab, int tid, int nt) {
+    F::setup(lds, gtab, tid, nt);
+    __bf16* ta = reinterpret_cast<__bf16*>(lds + F32_BYTES);
+    __bf16* tb = reinterpret_cast<__bf16*>(lds + F32_BYTES + A_BYTES);
+    for (int i = tid; i < MT * 16 * 32; i += nt) {
+      const int kk = i % 32, row = (i / 32) % 16, t = i / 512;
+      const int s = 4 * t + M::row_r(row), gi = M::row_g(row);
+      const bool ok = s < NS && kk < NDOF;
+      const float e = ok ? gtab[((gi + 4 * (s / C)) * 4 + s % C) * NDP + kk] : 0.0f;
+      ta[i] = (__bf16)e;
+    }
+    for (int i = tid; i < KSI * 16 * 32; i += nt) {
+      const int kk = i % 32, dof = (i / 32) % 16, ks = i / 512;
+      const int gk = kk / 8, s = 8 * ks + kk % 8;
+      const bool ok = s < NS && dof < NMF;
+      const float e = ok ? gtab[((gk + 4 * (s / C)) * 4 + s % C) * NDP + dof] : 0.0f;
+      tb[i] = (__bf16)e;
+    }
+  }
+
+  __device__ static inline void interpolate(const unsigned char* lds, const float (&ub)[NB], int g, int c16,
+                                            acc_t (&acc)[MT]) {
+    const bf8* ta = reinterpret_cast<const bf8*>(lds + F32_BYTES);
+    bf8 b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = (__bf16)ub[i];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const bf8 a = ta[(t * 16 + c16) * 4 + g];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc_t{0, 0, 0, 0}, 0, 0, 0);
+    }
+  }
+
+  __device__ static inline void integrate(const unsigned char* lds, const acc_t (&acc)[MT], int g, int c16, acc_t& v,
+                                          float (&vv)[NVA > 0 ? NVA : 1]) {
+    const bf8* tb = reinterpret_cast<const bf8*>(lds + F32_BYTES + A_BYTES);
+    v = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KSI; ++ks) {
+      bf8 b;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int s = 8 * ks + e;
+        b[e] = (__bf16)(s < NS ? acc[s < NS ? s / 4 : 0][s % 4] : 0.0f);
+      }
+      const bf8 a = tb[(ks * 16 + c16) * 4 + g];
+      v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, v, 0, 0, 0);
+    }
+    if (NVA > 0) {
+      const float* s_tab = reinterpret_cast<const float*>(lds);
+      float part[NVA > 0 ? NVA : 1];
+#pragma unroll
+      for (int jj = 0; jj < NVA; ++jj) part[jj] = 0.0f;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const float x = acc[s / 4][s % 4];
+        const float* e = s_tab + ((g + 4 * (s / C)) * C + s % C) * NDP + 16;
+#pragma unroll
+        for (int jj = 0; jj < NVA; ++jj) part[jj] += e[jj] * x;
+      }
+#pragma unroll
+      for (int jj = 0; jj < NVA; ++jj) {
+        float y = part[jj] + __shfl_xor(part[jj], 16);
+        vv[jj] = y + __shfl_xor(y, 32);
+      }
+    }
+  }
+};
+
+template <typename T, int NDOF, int NQ, int C, bool BF>
+struct EngineSel {
+  typedef Tile<T, NDOF, NQ, C> type;
+};
+template <int NDOF, int NQ, int C>
+struct EngineSel<float, NDOF, NQ, C, true> {
+  typedef TileBF<NDOF, NQ, C> type;
 };
 
 // Block range of this workgroup: the blocks are split into 8 contiguous
@@ -209,30 +338,24 @@ __device__ inline void cg_reduce(const CGDev& d, const T* __restrict__ s_slot, i
   }
 }
 
-template <typename T, int NDOF, int NQ, int C, int MODE>
+template <typename T, int NDOF, int NQ, int C, int MODE, bool BF>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* __restrict__ kappa,
           T* __restrict__ out, T* __restrict__ dk) {
-  using TL = Tile<T, NDOF, NQ, C>;
+  using TL = typename EngineSel<T, NDOF, NQ, C, BF>::type;
   using M = Mfma<T>;
   typedef typename M::acc_t acc_t;
-  constexpr int KS = TL::KS, KP = TL::KP, MT = TL::MT;
+  constexpr int NB = TL::NB, KP = TL::KP, MT = TL::MT;
   constexpr bool BWD = MODE == MODE_BACKWARD;
   extern __shared__ __align__(16) unsigned char smem[];
-  // LDS: table | weights | block slots | staged DoF values | local indices
-  T* s_tab = reinterpret_cast<T*>(smem);
-  T* s_qw = s_tab + TL::TAB;
+  // LDS: engine tables | weights | block slots | staged DoF values | local indices
+  unsigned char* s_eng = smem;
+  T* s_qw = reinterpret_cast<T*>(smem + TL::LDS_BYTES);
   T* s_slot = s_qw + TL::NPT;
   T* s_u = s_slot + kBlockCells * NDOF;
   uint16_t* s_lidx = reinterpret_cast<uint16_t*>(s_u + (BWD ? 2 : 1) * d.nbd_max);
-  {
-    const T* tab = static_cast<const T*>(d.tab);  // global layout [NPT][4][NDP]
-    for (int i = threadIdx.x; i < TL::TAB; i += kThreads) {
-      const int col = i % TL::NDP, c = (i / TL::NDP) % C, p = i / (TL::NDP * C);
-      s_tab[i] = tab[(p * 4 + c) * TL::NDP + col];
-    }
-    for (int i = threadIdx.x; i < TL::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
-  }
+  TL::setup(s_eng, static_cast<const T*>(d.tab), threadIdx.x, kThreads);
+  for (int i = threadIdx.x; i < TL::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, c16 = lane & 15;
   const int ncp = d.ncp, nc = d.n_cell;
@@ -325,24 +448,24 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
         for (int r = 0; r < 4; ++r) pv[r] = d.pos[M::row(g, r) * ncp + cell];
         if (TL::NVA > 0) pv[4] = d.pos[(16 + min(g, TL::NVA - 1)) * ncp + cell];
       }
-      T ub[KS];
-      T gb[BWD ? KS : 1];
+      T ub[NB];
+      T gb[BWD ? NB : 1];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const int j = 4 * ks + g;
-        const int l = (NDOF % 4 == 0 || j < NDOF) ? s_lidx[j * kBlockCells + cl] : 0;
-        ub[ks] = (NDOF % 4 == 0 || j < NDOF) ? s_u[l] : T(0);
-        if (BWD) gb[BWD ? ks : 0] = (NDOF % 4 == 0 || j < NDOF) ? s_u[d.nbd_max + l] : T(0);
+      for (int ks = 0; ks < NB; ++ks) {
+        const int j = TL::bdof(g, ks);
+        const int l = j < NDOF ? s_lidx[j * kBlockCells + cl] : 0;
+        ub[ks] = j < NDOF ? s_u[l] : T(0);
+        if (BWD) gb[BWD ? ks : 0] = j < NDOF ? s_u[d.nbd_max + l] : T(0);
       }
       acc_t acc[MT];
-      TL::interpolate(s_tab, ub, g, c16, acc);
+      TL::interpolate(s_eng, ub, g, c16, acc);
       acc_t accg[BWD ? MT : 1];
       if (BWD) {
-        T gtmp[KS];
+        T gtmp[NB];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) gtmp[ks] = gb[BWD ? ks : 0];
+        for (int ks = 0; ks < NB; ++ks) gtmp[ks] = gb[BWD ? ks : 0];
         acc_t tmp[MT];
-        TL::interpolate(s_tab, gtmp, g, c16, tmp);
+        TL::interpolate(s_eng, gtmp, g, c16, tmp);
 #pragma unroll
         for (int t = 0; t < MT; ++t) accg[BWD ? t : 0] = tmp[t];
       }
@@ -380,7 +503,7 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
       if (write_out) {
         acc_t v;
         T vv[TL::NVA > 0 ? TL::NVA : 1];
-        TL::integrate(s_tab, acc, g, c16, v, vv);
+        TL::integrate(s_eng, acc, g, c16, v, vv);
         if (valid) {
 #pragma unroll
           for (int r = 0; r < 4; ++r)
@@ -475,15 +598,15 @@ hipError_t launch_combine(const CGDev& d, const void* src, void* out, hipStream_
   return hipGetLastError();
 }
 
-template <typename T, int NDOF, int NQ, int C, int MODE>
+template <typename T, int NDOF, int NQ, int C, int MODE, bool BF>
 hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void* kappa, void* out, void* dk,
                         hipStream_t s, hipEvent_t* ev) {
-  using TL = Tile<T, NDOF, NQ, C>;
+  using TL = typename EngineSel<T, NDOF, NQ, C, BF>::type;
   const int ustage = (MODE == MODE_BACKWARD ? 2 : 1) * d.nbd_max;
-  const size_t lds = (size_t)(TL::TAB + TL::NPT + kBlockCells * NDOF + ustage) * sizeof(T) +
+  const size_t lds = (size_t)TL::LDS_BYTES + (size_t)(TL::NPT + kBlockCells * NDOF + ustage) * sizeof(T) +
                      (size_t)NDOF * kBlockCells * sizeof(uint16_t);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  auto kern = cg_kernel<T, NDOF, NQ, C, MODE>;
+  auto kern = cg_kernel<T, NDOF, NQ, C, MODE, BF>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
@@ -512,41 +635,46 @@ hipError_t launch_cg_vec(const CGDev& d, const void* kappa, void* out, hipStream
   return launch_combine<T, MODE>(d, nullptr, out, s);
 }
 
-template <typename T, int NDOF, int NQ>
+template <typename T, int NDOF, int NQ, bool BF>
 hipError_t launch_cg_mode(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
-                          void* dk, hipStream_t s, hipEvent_t* ev) {
+                          void* dk, hipStream_t s, hipEvent_t* ev, bool* supported) {
   const bool mass = d.sigma != 0.0;
   switch (mode) {
     case MODE_APPLY:
-      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_APPLY>(d, u, g, kappa, out, dk, s, ev)
-                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_APPLY>(d, u, g, kappa, out, dk, s, ev);
+      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_APPLY, BF>(d, u, g, kappa, out, dk, s, ev)
+                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_APPLY, BF>(d, u, g, kappa, out, dk, s, ev);
     case MODE_BACKWARD:
-      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_BACKWARD>(d, u, g, kappa, out, dk, s, ev)
-                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_BACKWARD>(d, u, g, kappa, out, dk, s, ev);
+      if (BF) {
+        *supported = false;
+        return hipSuccess;
+      }
+      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_BACKWARD, false>(d, u, g, kappa, out, dk, s, ev)
+                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_BACKWARD, false>(d, u, g, kappa, out, dk, s, ev);
     case MODE_DIAG: return launch_cg_vec<T, NDOF, NQ, MODE_DIAG>(d, kappa, out, s, ev);
     default: return launch_cg_vec<T, NDOF, NQ, MODE_LOAD>(d, kappa, out, s, ev);
   }
 }
 
-template <typename T>
+template <typename T, bool BF>
 hipError_t launch_cg_shape(const CGDev& d, int ndof, int nq, int mode, const void* u, const void* g,
                            const void* kappa, void* out, void* dk, hipStream_t s, bool* supported, hipEvent_t* ev) {
   *supported = true;
-  if (ndof == 4 && nq == 4) return launch_cg_mode<T, 4, 4>(d, mode, u, g, kappa, out, dk, s, ev);
-  if (ndof == 10 && nq == 4) return launch_cg_mode<T, 10, 4>(d, mode, u, g, kappa, out, dk, s, ev);
-  if (ndof == 10 && nq == 14) return launch_cg_mode<T, 10, 14>(d, mode, u, g, kappa, out, dk, s, ev);
-  if (ndof == 20 && nq == 14) return launch_cg_mode<T, 20, 14>(d, mode, u, g, kappa, out, dk, s, ev);
-  if (ndof == 20 && nq == 24) return launch_cg_mode<T, 20, 24>(d, mode, u, g, kappa, out, dk, s, ev);
+  if (ndof == 4 && nq == 4) return launch_cg_mode<T, 4, 4, BF>(d, mode, u, g, kappa, out, dk, s, ev, supported);
+  if (ndof == 10 && nq == 4) return launch_cg_mode<T, 10, 4, BF>(d, mode, u, g, kappa, out, dk, s, ev, supported);
+  if (ndof == 10 && nq == 14) return launch_cg_mode<T, 10, 14, BF>(d, mode, u, g, kappa, out, dk, s, ev, supported);
+  if (ndof == 20 && nq == 14) return launch_cg_mode<T, 20, 14, BF>(d, mode, u, g, kappa, out, dk, s, ev, supported);
+  if (ndof == 20 && nq == 24) return launch_cg_mode<T, 20, 24, BF>(d, mode, u, g, kappa, out, dk, s, ev, supported);
   *supported = false;
   return hipSuccess;
 }
 
 hipError_t launch_cg(const CGDev& d, int prec, int ndof, int nq, int mode, const void* u, const void* g,
                      const void* kappa, void* out, void* dk, hipStream_t s, bool* supported, hipEvent_t* ev) {
-  if (prec == PREC_F64) return launch_cg_shape<double>(d, ndof, nq, mode, u, g, kappa, out, dk, s, supported, ev);
-  if (prec == PREC_F32) return launch_cg_shape<float>(d, ndof, nq, mode, u, g, kappa, out, dk, s, supported, ev);
-  *supported = false;
-  return hipSuccess;
+  if (prec == PREC_F64)
+    return launch_cg_shape<double, false>(d, ndof, nq, mode, u, g, kappa, out, dk, s, supported, ev);
+  if (prec == PREC_F32)
+    return launch_cg_shape<float, false>(d, ndof, nq, mode, u, g, kappa, out, dk, s, supported, ev);
+  return launch_cg_shape<float, true>(d, ndof, nq, mode, u, g, kappa, out, dk, s, supported, ev);
 }
 
 // ---------------------------------------------------------------------------

@@ -140,3 +140,18 @@ def test_cg_backward_vs_oracle():
     dko = oracle.cg_kappa_grad(c["xyz"], c["tets"], 2, c["qp"], c["qw"], u, g, dofs=c["d"])
     dku = op.cell_data_to_user(dk).cpu().numpy()
     assert rel_err(dku, dko) <= 1e-12
+
+
+@pytest.mark.parametrize("p,qdeg,mass", [(3, 6, 0.0), (2, 4, 1.0), (3, 4, 0.0)])
+def test_cg_apply_bf16_operands(p, qdeg, mass):
+    """BF16 operands with FP32 accumulation: the error against the FP64 oracle
+    is reported, not gated at FP32 level.  The bound here (3e-2) only guards
+    against layout mistakes, which give O(1) errors; the measured value is
+    printed."""
+    c = setup_case(5, p, qdeg, kappa_sigma=1.0, mass=mass, precision="bf16in")
+    u = synth.uniform(0, synth.STREAM_U, c["A"].shape[0])
+    y = c["A"] @ u
+    v = run_apply(c, u)
+    err = rel_err(v, y[c["idx"]])
+    print(f"BF16-operand apply, P{p} degree-{qdeg} rule, sigma={mass}: relative error {err:.3e}")
+    assert err <= 3e-2
