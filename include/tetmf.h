@@ -124,6 +124,15 @@ int tetmf_op_create(const tetmf_mesh* mesh, const tetmf_op_desc* desc, tetmf_op*
 void tetmf_op_destroy(tetmf_op* op);
 int tetmf_op_info(const tetmf_op* op, tetmf_info* info);
 
+/* Host-only set-up check: runs the set-up of tetmf_op_create (numbering,
+ * blocks, face data) without touching any device and verifies the
+ * invariants the kernels rely on for every memory access (all indices in
+ * range, every (cell, node) slot used exactly once, every partial sum
+ * written exactly once).  Returns the status tetmf_op_create would return,
+ * or TETMF_ERR_DEVICE with a description if an invariant fails.  n_dofs and
+ * n_free (may be NULL) receive the sizes the op would have. */
+int tetmf_op_check(const tetmf_mesh* mesh, const tetmf_op_desc* desc, int64_t* n_dofs, int64_t* n_free);
+
 /* Maps from library order to user order (host buffers, any may be NULL):
  *  cell_perm [n_cell]: user cell id of library cell i
  *  dof_xyz   [n_dofs][3]: coordinates of each DoF (library numbering)

@@ -74,6 +74,8 @@ _SIGS = {
     "tetmf_op_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(OpDesc), ctypes.POINTER(ctypes.c_void_p)]),
     "tetmf_op_destroy": (None, [ctypes.c_void_p]),
     "tetmf_op_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Info)]),
+    "tetmf_op_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(OpDesc), ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.POINTER(ctypes.c_int64)]),
     "tetmf_op_numbering": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "tetmf_cell_data_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                               ctypes.c_void_p]),
@@ -164,6 +166,41 @@ class Mesh:
         if getattr(self, "_h", None) and _LIB is not None:
             _LIB.tetmf_mesh_destroy(self._h)
             self._h = None
+
+
+def _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, device):
+    qp, qw = (np.ascontiguousarray(a, dtype=np.float64) for a in qrule)
+    d = OpDesc()
+    d.kind = _KIND[kind]
+    d.degree = int(degree)
+    d.bc = _BC[bc]
+    d.precision = _PREC[precision]
+    d.ordering = _ORDER[ordering]
+    d.n_q = qw.size
+    d.q_points = qp.ctypes.data
+    d.q_weights = qw.ctypes.data
+    keep = [qp, qw]
+    if frule is not None:
+        fp, fw = (np.ascontiguousarray(a, dtype=np.float64) for a in frule)
+        d.n_qf = fw.size
+        d.qf_points = fp.ctypes.data
+        d.qf_weights = fw.ctypes.data
+        keep += [fp, fw]
+    d.sigma = float(sigma)
+    d.eta = float(eta)
+    d.device = int(device)
+    return d, keep
+
+
+def check_setup(mesh, degree, qrule, kind="cg", frule=None, precision="f64", bc="neumann", sigma=0.0, eta=1.0,
+                ordering="locality"):
+    """Host-only run of the operator set-up with its invariant checks (no GPU
+    needed); returns (n_dofs, n_free) or raises TetmfError."""
+    d, keep = _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, 0)
+    nd, nf = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().tetmf_op_check(mesh._h, ctypes.byref(d), ctypes.byref(nd), ctypes.byref(nf)))
+    del keep
+    return nd.value, nf.value
 
 
 class Operator:

@@ -445,7 +445,9 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
       uint16_t pv[4 + TL::NVA];
       if (write_out) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) pv[r] = d.pos[M::row(g, r) * ncp + cell];
+        // rows beyond the cell's DoFs (fewer than 16 at p <= 2) have no slot
+        for (int r = 0; r < 4; ++r)
+          pv[r] = (TL::NMF == 16 || M::row(g, r) < TL::NMF) ? d.pos[M::row(g, r) * ncp + cell] : uint16_t(0);
         if (TL::NVA > 0) pv[4] = d.pos[(16 + min(g, TL::NVA - 1)) * ncp + cell];
       }
       T ub[NB];

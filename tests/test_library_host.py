@@ -75,3 +75,40 @@ def test_mesh_errors(L):
     with pytest.raises(L.TetmfError) as e:
         L.Mesh(xyz, three)
     assert e.value.status == -3
+
+
+@pytest.mark.parametrize("n,p,qdeg,sigma,bc,ordering", [
+    (5, 1, 2, 0.0, "neumann", "locality"),
+    (6, 2, 4, 1.0, "dirichlet", "locality"),
+    (6, 3, 6, 0.0, "neumann", "as_given"),
+    (4, 3, 4, 0.0, "dirichlet", "locality"),
+])
+def test_host_setup_invariants(L, n, p, qdeg, sigma, bc, ordering):
+    """tetmf_op_check runs the CG block set-up on the host and verifies every
+    index the kernels dereference (no GPU involved)."""
+    import oracle
+    xyz, tets = synth.kuhn_cube_mesh(n, 0.15)
+    m = L.Mesh(xyz, tets)
+    nd, nf = L.check_setup(m, p, synth.tet_rule(qdeg), sigma=sigma, bc=bc, ordering=ordering)
+    d = oracle.cg_dofs(xyz, tets, p)
+    assert nd == d["xyz"].shape[0]
+    assert nf == (nd if bc == "neumann" else int((~d["constrained"]).sum()))
+
+
+def test_host_setup_shuffled_and_dg(L):
+    xyz, tets = synth.shuffle_mesh(*synth.kuhn_cube_mesh(5, 0.15), seed=1)
+    m = L.Mesh(xyz, tets)
+    assert L.check_setup(m, 3, synth.tet_rule(6), ordering="as_given")[0] == 16 ** 3
+    nd, _ = L.check_setup(m, 3, synth.tet_rule(6), kind="dg", frule=synth.tri_rule(6), bc="dirichlet")
+    assert nd == 20 * tets.shape[0]
+
+
+def test_host_setup_rejects_unsupported(L):
+    xyz, tets = synth.kuhn_cube_mesh(2)
+    m = L.Mesh(xyz, tets)
+    with pytest.raises(L.TetmfError) as e:
+        L.check_setup(m, 3, synth.tet_rule(2))  # no kernel for P3 with 4 points
+    assert e.value.status == -4
+    with pytest.raises(L.TetmfError) as e:
+        L.check_setup(m, 3, synth.tet_rule(6), kind="dg")  # face rule missing
+    assert e.value.status == -1
