@@ -33,7 +33,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense matrix-core peaks
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16in": 2500.0}   # MI355X dense matrix-core peaks
 PEAK_HBM_GBS = 8000.0
 METRIC = "DoFs/s per operator apply, p=3 CG, FP64 vs FP32-MFMA; % of roofline"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_apply_p3_n64_traffic.txt")
@@ -87,10 +87,19 @@ def time_gpu(op, kl, u, steps, warmup):
 
 
 def roofline(op, prec, avg_ms):
+    """Roofline of the cell kernel.  FP64 and FP32 are compute-bound by the
+    algorithmic intensity (flops/byte above the ridge point); with BF16
+    operands the matrix-core peak is 16x higher and the HBM roof binds."""
     flops = op.info["flops_per_apply"]
     bytes_alg = op.info["bytes_per_apply"]
     achieved = flops / (avg_ms * 1e-3) / 1e12
     traffic = read_traffic(prec)
+    gbs = bytes_alg / (avg_ms * 1e-3) / 1e9
+    if prec == "bf16in":
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic, "algorithmic_flops": flops,
+                "algorithmic_bytes": bytes_alg, "mfma_achieved_TFLOPs": round(achieved, 3),
+                "kernel_ms": round(avg_ms, 5)}
     return {
         "bound": "mfma",
         "achieved": round(achieved, 3),
@@ -149,13 +158,121 @@ def copy_calibration(mib=1024, reps=3):
     print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "reps": reps}), flush=True)
 
 
+def _time_call(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_c2(args):
+    """SIPG P3 apply, 32^3 x 6 cells, lognormal(0, 0.5) cell and face coefficients, Dirichlet mirror."""
+    import torch
+
+    import paper_2509_10226_amd as tm
+    import synth
+    n = 32
+    xyz, tets = synth.kuhn_cube_mesh(n, 0.15, 0)
+    qp, qw = synth.tet_rule(6)
+    fp, fw = synth.tri_rule(6)
+    mesh = tm.Mesh(xyz, tets)
+    kc = synth.lognormal(0, synth.STREAM_KAPPA_CELL, (tets.shape[0], qw.size), sigma=0.5)
+    kf = synth.lognormal(0, synth.STREAM_KAPPA_FACE, (mesh.n_face, fw.size), sigma=0.5)
+    op = tm.Operator(mesh, 3, (qp, qw), kind="dg", frule=(fp, fw), bc="dirichlet")
+    klc = op.cell_data_to_library(torch.from_numpy(kc).cuda())
+    klf = torch.from_numpy(kf.T.copy()).cuda()
+    u = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda") * 2 - 1
+    out = torch.empty_like(u)
+    op.profile(True)
+    ms = _time_call(lambda: op.apply(u, klc, klf, out=out), args.steps, args.warmup)
+    op.profile(False)
+    kms, nl = op.profile_read()
+    kms /= nl
+    print(json.dumps({"metric": "DoFs/s per SIPG operator apply, P3, FP64", "value": round(op.n_dofs / (ms * 1e-3), 1),
+                      "unit": "DoFs/s", "ms_per_step": round(ms, 5), "dtype": "f64",
+                      "config": {"workload": f"DG SIPG P3, {n}^3x6 Kuhn tets, lognormal(0,0.5) cell+face kappa, "
+                                             f"Dirichlet mirror, 24/12-point rules", "n_dofs": op.n_dofs},
+                      "roofline": roofline(op, "f64", kms)}), flush=True)
+
+
+def bench_c4(args):
+    """CG P2 Helmholtz (stiffness + 1.0 mass), 48^3 x 6 cells: forward and backward kernels."""
+    import torch
+
+    import paper_2509_10226_amd as tm
+    import synth
+    n = 48
+    xyz, tets = synth.kuhn_cube_mesh(n, 0.15, 0)
+    qp, qw = synth.tet_rule(4)
+    kap = synth.lognormal(0, synth.STREAM_KAPPA_CELL, (tets.shape[0], qw.size), sigma=0.5)
+    op = tm.Operator(tm.Mesh(xyz, tets), 2, (qp, qw), sigma=1.0)
+    kl = op.cell_data_to_library(torch.from_numpy(kap).cuda())
+    u = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda") * 2 - 1
+    g = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda") * 2 - 1
+    op.profile(True)
+    ms_f = _time_call(lambda: op.apply(u, kl), args.steps, args.warmup)
+    op.profile(False)
+    kf, nf = op.profile_read()
+    op.profile(True)
+    ms_b = _time_call(lambda: op.backward(u, g, kl), args.steps, args.warmup)
+    op.profile(False)
+    kb, nb = op.profile_read()
+    print(json.dumps({"metric": "DoFs/s per apply and per backward (du, dkappa), CG P2 Helmholtz, FP64",
+                      "value": round(op.n_dofs / (ms_f * 1e-3), 1), "unit": "DoFs/s",
+                      "ms_forward": round(ms_f, 5), "ms_backward": round(ms_b, 5),
+                      "kernel_ms_forward": round(kf / nf, 5), "kernel_ms_backward": round(kb / nb, 5),
+                      "backward_DoFs_per_s": round(op.n_dofs / (ms_b * 1e-3), 1), "dtype": "f64",
+                      "config": {"workload": f"CG P2 stiffness + 1.0 mass, {n}^3x6 Kuhn tets, lognormal(0,0.5) kappa, "
+                                             f"14-point rule", "n_dofs": op.n_dofs},
+                      "roofline": roofline(op, "f64", kf / nf)}), flush=True)
+
+
+def bench_c5(args):
+    """Time to a true relative residual of 1e-10: FP32-inner iterative refinement vs FP64 PCG."""
+    import torch
+
+    import paper_2509_10226_amd as tm
+    import synth
+    n = 64
+    xyz, tets = synth.kuhn_cube_mesh(n, 0.15, 0)
+    qp, qw = synth.tet_rule(6)
+    mesh = tm.Mesh(xyz, tets)
+    op64 = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet")
+    res = {}
+    for inner in ("f32", "bf16in", None):
+        opi = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet", precision=inner) if inner else None
+        b = op64.load_vector()
+        op64.solve(b, inner=opi, rtol=1e-10, max_inner=20000)  # warm-up (allocates solver scratch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, st, ok = op64.solve(b, inner=opi, rtol=1e-10, max_inner=20000)
+        torch.cuda.synchronize()
+        st["solver_seconds"] = st.pop("seconds")
+        res[inner or "f64"] = dict(wall_seconds=round(time.perf_counter() - t0, 4), converged=ok, **st)
+    print(json.dumps({"metric": "time to relative residual 1e-10, CG P3 Dirichlet Poisson f=1",
+                      "value": res["f32"]["wall_seconds"], "unit": "s", "higher_is_better": False,
+                      "config": {"workload": f"CG P3, {n}^3x6 Kuhn tets, kappa=1, 24-point rule, Jacobi-PCG",
+                                 "n_dofs": op64.n_dofs, "n_free": op64.n_free},
+                      "fp32_inner_ir": res["f32"], "bf16_inner_ir": res["bf16in"], "fp64_pcg": res["f64"],
+                      "speedup_fp32_ir_vs_fp64": round(res["f64"]["wall_seconds"] / res["f32"]["wall_seconds"], 3)}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=64, help="cubes per axis (64 = the measured workload)")
-    ap.add_argument("--precisions", default="f64,f32")
+    ap.add_argument("--precisions", default="f64,f32,bf16in")
+    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5"],
+                    help="c3 (default): the measured workload; c2/c4/c5: secondary measurements, "
+                         "each printed as its own JSON line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -168,6 +285,9 @@ def main():
     import paper_2509_10226_amd as tm
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.config != "c3":
+        {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.config](args)
         return
     dev = torch.device("cuda", 0)
     xyz, tets, qp, qw, kap = build_workload(args.n)

@@ -201,10 +201,11 @@ int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* op_inner, const v
                 const double* b, double* x, const tetmf_solve_opts* opts, tetmf_solve_stats* stats,
                 void* stream);
 
-/* Measurement aid.  While enabled, the op records a HIP event pair on the
- * caller's stream around every launch of its main kernel (the cell kernel of
- * apply, backward, diagonal and load vector; the cell-and-face kernel for
- * DG).  tetmf_op_profile(op, 1) starts a new measurement (events are created
+/* Measurement aid.  While enabled, every launch of the op's main kernel (the
+ * cell kernel of apply, backward, diagonal and load vector; the
+ * cell-and-face kernel for DG) carries a HIP event pair that takes the start
+ * and end timestamps of that dispatch on the caller's stream, so the elapsed
+ * time is the kernel's own duration (no separate marker packets).  tetmf_op_profile(op, 1) starts a new measurement (events are created
  * on demand and reused), tetmf_op_profile(op, 0) stops recording.
  * tetmf_op_profile_read synchronises on the recorded events and returns the
  * summed kernel time in milliseconds and the number of launches recorded. */

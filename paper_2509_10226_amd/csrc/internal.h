@@ -66,7 +66,8 @@ struct DGDev {
 };
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
-// ev: NULL, or two events recorded on s just before and after the main kernel.
+// ev: NULL, or two events that take the start and end timestamps of the main
+// kernel's dispatch (hipExtLaunchKernelGGL).
 hipError_t launch_cg(const CGDev& d, int prec, int ndof, int nq, int mode, const void* u, const void* g,
                      const void* kappa, void* out, void* dkappa, hipStream_t s, bool* supported,
                      hipEvent_t* ev);

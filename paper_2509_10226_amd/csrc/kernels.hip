@@ -25,6 +25,8 @@
 // the 16 lanes that read one column on distinct banks).
 #include "internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 namespace tetmf {
@@ -612,11 +614,11 @@ hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
-  if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)g, (const T*)kappa, (T*)out,
-                     (T*)dk);
+  // With ev, the events take the start and end timestamps of this dispatch
+  // itself, so their elapsed time is the kernel's duration alone.
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
+                        (const T*)u, (const T*)g, (const T*)kappa, (T*)out, (T*)dk);
   e = hipGetLastError();
-  if (ev) (void)hipEventRecord(ev[1], s);
   if (e != hipSuccess || out == nullptr) return e;
   return launch_combine<T, MODE>(d, MODE == MODE_BACKWARD ? g : u, out, s);
 }
@@ -629,10 +631,9 @@ hipError_t launch_cg_vec(const CGDev& d, const void* kappa, void* out, hipStream
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
-  if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)kappa, (T*)out);
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
+                        (const T*)kappa, (T*)out);
   e = hipGetLastError();
-  if (ev) (void)hipEventRecord(ev[1], s);
   if (e != hipSuccess) return e;
   return launch_combine<T, MODE>(d, nullptr, out, s);
 }
@@ -880,10 +881,9 @@ hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, (ntiles + kWaves - 1) / kWaves);
-  if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)kc, (const T*)kf, (T*)v);
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
+                        (const T*)u, (const T*)kc, (const T*)kf, (T*)v);
   e = hipGetLastError();
-  if (ev) (void)hipEventRecord(ev[1], s);
   return e;
 }
 
