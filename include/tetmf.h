@@ -15,7 +15,7 @@
  * the per-point geometry J^{-1} J^{-T} |det J| w_q and the coefficient
  * kappa_q, E^T integrates against the test functions and G_e^T scatters back.
  * The bilinear forms are eq. (2) (Poisson), eq. (3) (SIPG) and the
- * Helmholtz-type form of eq. (16) (stiffness plus sigma times mass).
+ * Helmholtz-type form of eq. (19) (stiffness plus sigma times mass).
  *
  * Conventions shared by every entry point
  *  - Status codes: 0 = OK, > 0 = non-fatal status, < 0 = error.  No entry

@@ -9,7 +9,7 @@ inputs produced by ``synth``.
 What it computes is the definition the matrix-free method reaches up to
 rounding order: the assembled global sparse matrix of the weak forms of
 eq. (2) (continuous Galerkin Poisson), eq. (3) (SIPG discontinuous Galerkin)
-and the Helmholtz-type form of eq. (16) (stiffness plus a mass term), built
+and the Helmholtz-type form of eq. (19) (stiffness plus a mass term), built
 cell by cell from element matrices evaluated with the shared quadrature rule,
 and then applied with a sparse matrix-vector product (the matrix-based
 comparison of Sec. 3.2).

@@ -2,7 +2,8 @@
 load vectors, straight from the weak forms.
 
 Continuous Galerkin (eq. (2), with a coefficient kappa per quadrature point
-and an optional mass term sigma (u, v) as in the Helmholtz-type eq. (16)):
+and an optional mass term sigma (u, v) as in the Helmholtz-type eq. (19),
+the velocity step of the dual splitting in Sec. 4.2):
 
     A_e[i, j] = sum_q w_q |det J| ( kappa_{e,q} grad phi_i . grad phi_j
                                     + sigma phi_i phi_j )  at x_q,
