@@ -308,6 +308,15 @@ static int persistent_grid(const void* kern, size_t lds, int work) {
 //    shared DoFs become partial sums that cg_combine adds in block order.
 // Every sum has a fixed order, so the result is bitwise reproducible.
 
+// Thread index hidden from loop-invariant code motion: values derived from it
+// inside a phase are not kept live across the other phases of the block loop
+// (the compute phase needs every register for the matrix-core tiles).
+__device__ inline int phase_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Sum the slots of every block DoF (fixed order) and store them.
 template <typename T>
 __device__ inline void cg_reduce(const CGDev& d, const T* __restrict__ s_slot, int nbd, int npriv, int ps, int oo,
@@ -358,8 +367,6 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
   uint16_t* s_lidx = reinterpret_cast<uint16_t*>(s_u + (BWD ? 2 : 1) * d.nbd_max);
   TL::setup(s_eng, static_cast<const T*>(d.tab), threadIdx.x, kThreads);
   for (int i = threadIdx.x; i < TL::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
   const int ncp = d.ncp, nc = d.n_cell;
   const T* geo = static_cast<const T*>(d.geo);
   const T sigma = (T)d.sigma;
@@ -424,6 +431,10 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
     __syncthreads();
 #pragma unroll 1
     for (int tt = 0; tt < kTilesPerWave; ++tt) {
+      // lane coordinates re-derived per tile (not held across the block loop)
+      const int tid = phase_tid();
+      const int lane = tid & 63, wave = tid >> 6;
+      const int g = lane >> 4, c16 = lane & 15;
       const int cl = (wave + tt * kWaves) * kTile + c16;
       const int cell = b * kBlockCells + cl;
       const bool valid = cell < nc;
