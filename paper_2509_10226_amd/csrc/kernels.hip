@@ -59,6 +59,37 @@ struct Mfma<float> {
   __device__ static constexpr int row_r(int i) { return i & 3; }
 };
 
+// Sum of x over the four 16-lane rows of the wave, (r0 + r1) + (r2 + r3) in
+// every lane, with the gfx950 lane-swap instructions (no LDS round trip).
+// permlane16_swap(x, x) gives {x of rows 0,0,2,2; x of rows 1,1,3,3} and
+// permlane32_swap(y, y) gives {y of the lower half twice; of the upper half}.
+__device__ inline uint32_t row_swap16_lo(uint32_t x, uint32_t& hi) {
+  const auto q = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+  hi = q[1];
+  return q[0];
+}
+__device__ inline uint32_t row_swap32_lo(uint32_t x, uint32_t& hi) {
+  const auto q = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+  hi = q[1];
+  return q[0];
+}
+__device__ inline float sum_rows(float x) {
+  uint32_t h16, h32;
+  const float y = __uint_as_float(row_swap16_lo(__float_as_uint(x), h16)) + __uint_as_float(h16);
+  return __uint_as_float(row_swap32_lo(__float_as_uint(y), h32)) + __uint_as_float(h32);
+}
+__device__ inline double sum_rows(double x) {
+  const uint64_t b = __double_as_longlong(x);
+  uint32_t h0, h1;
+  const uint32_t l0 = row_swap16_lo((uint32_t)b, h0), l1 = row_swap16_lo((uint32_t)(b >> 32), h1);
+  const double y = __longlong_as_double((long long)(((uint64_t)l1 << 32) | l0)) +
+                   __longlong_as_double((long long)(((uint64_t)h1 << 32) | h0));
+  const uint64_t c = __double_as_longlong(y);
+  const uint32_t m0 = row_swap32_lo((uint32_t)c, h0), m1 = row_swap32_lo((uint32_t)(c >> 32), h1);
+  return __longlong_as_double((long long)(((uint64_t)m1 << 32) | m0)) +
+         __longlong_as_double((long long)(((uint64_t)h1 << 32) | h0));
+}
+
 // Layout of one 16-cell tile in the matrix-core registers.  Quadrature point
 // p is handled by lane group p % 4 (as its k-th point, k = p / 4); item
 // s = C k + c of a lane group is component c of its k-th point (components
@@ -153,10 +184,7 @@ struct Tile {
         for (int jj = 0; jj < NVA; ++jj) part[jj] += e[jj] * x;
       }
 #pragma unroll
-      for (int jj = 0; jj < NVA; ++jj) {
-        T y = part[jj] + __shfl_xor(part[jj], 16);
-        vv[jj] = y + __shfl_xor(y, 32);
-      }
+      for (int jj = 0; jj < NVA; ++jj) vv[jj] = sum_rows(part[jj]);
     }
   }
 };
@@ -250,10 +278,7 @@ struct TileBF {
         for (int jj = 0; jj < NVA; ++jj) part[jj] += e[jj] * x;
       }
 #pragma unroll
-      for (int jj = 0; jj < NVA; ++jj) {
-        float y = part[jj] + __shfl_xor(part[jj], 16);
-        vv[jj] = y + __shfl_xor(y, 32);
-      }
+      for (int jj = 0; jj < NVA; ++jj) vv[jj] = sum_rows(part[jj]);
     }
   }
 };
