@@ -263,6 +263,70 @@ def bench_c5(args):
           flush=True)
 
 
+def bench_order(args):
+    """Cell and vertex order: the CG P3 FP64 apply of the measured workload on the
+    mesh as generated, on a seeded random relabelling of its cells and vertices
+    (the stand-in for an unordered mesh from a mesh generator) with the
+    library's locality ordering, and on that relabelling taken as given."""
+    import torch
+
+    import paper_2509_10226_amd as tm
+    import synth
+    xyz, tets, qp, qw, kap = build_workload(args.n)
+    variants = {"native_locality": (False, "locality"), "shuffled_locality": (True, "locality"),
+                "shuffled_as_given": (True, "as_given")}
+    if args.order_variant != "all":
+        variants = {args.order_variant: variants[args.order_variant]}
+    res = {}
+    for name, (shuffle, ordering) in variants.items():
+        # coefficients are drawn per cell of the mesh as numbered (same seed and
+        # stream for both numberings)
+        x, t = synth.shuffle_mesh(xyz, tets, 0) if shuffle else (xyz, tets)
+        op = tm.Operator(tm.Mesh(x, t), 3, (qp, qw), ordering=ordering)
+        kl = op.cell_data_to_library(torch.from_numpy(kap).cuda())
+        g = torch.Generator(device="cpu").manual_seed(2)
+        u = (torch.rand(op.n_dofs, generator=g, dtype=torch.float64) * 2 - 1).cuda()
+        ms_step, ms_kernel, _ = time_gpu(op, kl, u, args.steps, args.warmup)
+        res[name] = {"DoFs_per_s": round(op.n_dofs / (ms_step * 1e-3), 1), "ms_per_step": round(ms_step, 5),
+                     "kernel_ms": round(ms_kernel, 5), "partials": op.info["n_partials"]}
+        del op
+    print(json.dumps({"metric": "DoFs/s per operator apply vs cell order, CG P3 FP64", "unit": "DoFs/s",
+                      "dtype": "f64", "config": {"workload": f"CG P3 Poisson, {args.n}^3x6 Kuhn tets, lognormal(0,1) "
+                                                             "kappa, 24-point rule; shuffle seed 0"},
+                      "variants": res}), flush=True)
+
+
+def bench_f1(args):
+    """Reduced cell integration (a rule exact to degree 2p - 2 = 4, 14 points)
+    against the degree-6 rule on the measured workload's mesh, FP64 and FP32."""
+    import torch
+
+    import paper_2509_10226_amd as tm
+    import synth
+    xyz, tets = synth.kuhn_cube_mesh(args.n, 0.15, 0)
+    mesh = tm.Mesh(xyz, tets)
+    res = {}
+    for deg in (6, 4):
+        qp, qw = synth.tet_rule(deg)
+        kap = synth.lognormal(0, synth.STREAM_KAPPA_CELL, (tets.shape[0], qw.size), mu=0.0, sigma=1.0)
+        for prec in ("f64", "f32"):
+            op = tm.Operator(mesh, 3, (qp, qw), precision=prec)
+            kl = op.cell_data_to_library(torch.from_numpy(kap).cuda())
+            g = torch.Generator(device="cpu").manual_seed(2)
+            u = (torch.rand(op.n_dofs, generator=g, dtype=torch.float64) * 2 - 1).to("cuda", op.dtype)
+            ms_step, ms_kernel, _ = time_gpu(op, kl, u, args.steps, args.warmup)
+            res[f"degree{deg}_{prec}"] = {"n_q": int(qw.size), "DoFs_per_s": round(op.n_dofs / (ms_step * 1e-3), 1),
+                                          "ms_per_step": round(ms_step, 5), "kernel_ms": round(ms_kernel, 5),
+                                          "roofline": roofline(op, prec, ms_kernel)}
+            del op
+    print(json.dumps({"metric": "DoFs/s per operator apply, CG P3, degree-4 (reduced) vs degree-6 cell rule",
+                      "unit": "DoFs/s", "config": {"workload": f"CG P3 Poisson, {args.n}^3x6 Kuhn tets, lognormal(0,1) "
+                                                                 "kappa per point of each rule"},
+                      "variants": res,
+                      "speedup_f64": round(res["degree4_f64"]["DoFs_per_s"] / res["degree6_f64"]["DoFs_per_s"], 3)}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,9 +334,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=64, help="cubes per axis (64 = the measured workload)")
     ap.add_argument("--precisions", default="f64,f32,bf16in")
-    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5"],
-                    help="c3 (default): the measured workload; c2/c4/c5: secondary measurements, "
+    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5", "order", "f1"],
+                    help="c3 (default): the measured workload; c2/c4/c5/order/f1: secondary measurements, "
                          "each printed as its own JSON line")
+    ap.add_argument("--order-variant", default="all",
+                    choices=["all", "native_locality", "shuffled_locality", "shuffled_as_given"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
@@ -287,7 +353,7 @@ def main():
         copy_calibration()
         return
     if args.config != "c3":
-        {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5}[args.config](args)
+        {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "order": bench_order, "f1": bench_f1}[args.config](args)
         return
     dev = torch.device("cuda", 0)
     xyz, tets, qp, qw, kap = build_workload(args.n)

@@ -57,6 +57,24 @@ def test_cg_apply_variable_kappa(p, qdeg, n, precision):
     assert rel_err(v, y[c["idx"]]) <= TOL[precision]
 
 
+def test_cg_reduced_rule_unit_kappa():
+    """P3 apply with the 14-point rule exact to degree 4 (modified integration,
+    Sec. 3.3) and a unit coefficient equals the oracle's stiffness built with
+    the degree-6 rule: a check through a different quadrature."""
+    tm = _tm()
+    n, p = 4, 3
+    xyz, tets = synth.kuhn_cube_mesh(n, 0.15, 0)
+    qf, wf = synth.tet_rule(6)
+    A, d = oracle.assemble_cg(xyz, tets, p, qf, wf)
+    qr, wr = synth.tet_rule(4)
+    op = tm.Operator(tm.Mesh(xyz, tets), p, (qr, wr))
+    _, dxyz, _ = op.numbering()
+    idx = cg_map(dxyz, d["xyz"], 1.0 / n)
+    u = synth.uniform(0, synth.STREAM_U, A.shape[0])
+    v = op.apply(torch.from_numpy(u[idx]).cuda()).cpu().numpy()
+    assert rel_err(v, (A @ u)[idx]) <= 1e-12
+
+
 def test_cg_c1_config():
     """CG P2 Poisson stiffness, 8^3 x 6 Kuhn tets, jitter 0.15h seed 0, kappa = 1, degree-4 rule."""
     c = setup_case(8, 2, 4)
