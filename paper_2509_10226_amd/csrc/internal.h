@@ -86,12 +86,16 @@ hipError_t vec_dot(int prec, const void* x, const void* y, int64_t n, double* pa
 hipError_t vec_cast(int prec_src, const void* src, int prec_dst, void* dst, int64_t n, hipStream_t s);
 // r = b - a (FP64)
 hipError_t vec_sub(const double* b, const double* a, double* r, int64_t n, hipStream_t s);
-// PCG steps with device-resident scalars (see kernels.hip).
-hipError_t pcg_update_xr(int prec, void* x, void* r, const void* p, const void* q, const double* rz,
-                         const double* pq, int64_t n, hipStream_t s);
-hipError_t pcg_precond(int prec, void* z, const void* r, const void* dinv, int64_t n, hipStream_t s);
-hipError_t pcg_update_p(int prec, void* p, const void* z, const double* rz_new, const double* rz_old,
-                        int64_t n, hipStream_t s);
+// Fused Jacobi-PCG steps with device-resident FP64 scalars (kernels.hip).
+// part: at least 3 * 512 doubles of partial sums.
+// pcg_init: x = 0, r = rhs, z = dinv r, p = z, *rz = r.z, *rr = r.r.
+hipError_t pcg_init(int prec, const void* rhs, const void* dinv, void* x, void* r, void* z, void* p, double* part,
+                    double* rz, double* rr, int64_t n, hipStream_t s);
+// One iteration after q = A p: alpha = rz_old / p.q, x += alpha p,
+// r -= alpha q, z = dinv r, *rz_new = r.z, beta = rz_new / rz_old,
+// p = z + beta p, *rr = r.r.  rz_old and rz_new must be distinct.
+hipError_t pcg_iteration(int prec, void* x, void* r, void* z, void* p, const void* q, const void* dinv, double* part,
+                         const double* rz_old, double* rz_new, double* rr, int64_t n, hipStream_t s);
 hipError_t vec_recip(int prec, void* d, int64_t n, hipStream_t s);
 hipError_t vec_axpy_f64(double* x, const void* d, int prec_d, int64_t n, hipStream_t s);
 

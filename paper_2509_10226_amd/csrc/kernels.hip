@@ -1020,26 +1020,129 @@ __global__ void sub_kernel(const double* __restrict__ b, const double* __restric
   for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) r[i] = b[i] - a[i];
 }
 
+// Fused Jacobi-PCG steps.  kVecBlocks blocks of 256 threads, grid-stride
+// loops in a fixed order; every block writes one FP64 partial sum per dot
+// product, and the consumers add the kVecBlocks partials in a fixed order
+// (each consuming block computes the identical total), so all scalars are
+// bitwise reproducible.
+constexpr int kVecBlocks = 512;
+
+// Fixed-order sum over the block (256 threads) of v; the result in all threads.
+__device__ inline double block_sum256(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Sum of the kVecBlocks partials (fixed order), in all threads.
+__device__ inline double sum_partials(const double* __restrict__ part, double* sh) {
+  double v = 0;
+  for (int i = threadIdx.x; i < kVecBlocks; i += 256) v += part[i];
+  return block_sum256(v, sh);
+}
+
+// x = 0, r = rhs, z = dinv r, p = z; partials of r.z and r.r.
 template <typename T>
-__global__ void update_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
-                          const double* rz, const double* pq, long n) {
-  const double alpha = *rz / *pq;
-  const T a = (T)alpha;
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-    x[i] += a * p[i];
-    r[i] -= a * q[i];
+__global__ void __launch_bounds__(256) pcg_init_kernel(const T* __restrict__ rhs, const T* __restrict__ dinv,
+                                                       T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+                                                       T* __restrict__ p, double* __restrict__ part_rz,
+                                                       double* __restrict__ part_rr, long n) {
+  __shared__ double sh[256];
+  double srz = 0, srr = 0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256) {
+    const T ri = rhs[i], zi = dinv[i] * ri;
+    x[i] = T(0);
+    r[i] = ri;
+    z[i] = zi;
+    p[i] = zi;
+    srz += (double)ri * (double)zi;
+    srr += (double)ri * (double)ri;
+  }
+  srz = block_sum256(srz, sh);
+  srr = block_sum256(srr, sh);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = srz;
+    part_rr[blockIdx.x] = srr;
   }
 }
 
-template <typename T>
-__global__ void precond_kernel(T* __restrict__ z, const T* __restrict__ r, const T* __restrict__ dinv, long n) {
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) z[i] = dinv[i] * r[i];
+// rz = sum(part_rz), rr = sum(part_rr) (one block).
+__global__ void __launch_bounds__(256) pcg_scalars_kernel(const double* __restrict__ part_rz,
+                                                          const double* __restrict__ part_rr, double* __restrict__ rz,
+                                                          double* __restrict__ rr) {
+  __shared__ double sh[256];
+  const double a = sum_partials(part_rz, sh), b = sum_partials(part_rr, sh);
+  if (threadIdx.x == 0) {
+    *rz = a;
+    *rr = b;
+  }
 }
 
+// partials of p.q
 template <typename T>
-__global__ void update_p(T* __restrict__ p, const T* __restrict__ z, const double* rz_new, const double* rz_old, long n) {
-  const T beta = (T)(*rz_new / *rz_old);
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) p[i] = z[i] + beta * p[i];
+__global__ void __launch_bounds__(256) pcg_dot_kernel(const T* __restrict__ a, const T* __restrict__ b,
+                                                      double* __restrict__ part, long n) {
+  __shared__ double sh[256];
+  double v = 0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256)
+    v += (double)a[i] * (double)b[i];
+  v = block_sum256(v, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// alpha = rz / p.q;  x += alpha p, r -= alpha q, z = dinv r;  partials of r.z, r.r
+template <typename T>
+__global__ void __launch_bounds__(256) pcg_xr_kernel(T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
+                                                     const T* __restrict__ p, const T* __restrict__ q,
+                                                     const T* __restrict__ dinv, const double* __restrict__ part_pq,
+                                                     const double* __restrict__ rz, double* __restrict__ part_rz,
+                                                     double* __restrict__ part_rr, long n) {
+  __shared__ double sh[256];
+  const T a = (T)(*rz / sum_partials(part_pq, sh));
+  double srz = 0, srr = 0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    const T zi = dinv[i] * ri;
+    r[i] = ri;
+    z[i] = zi;
+    srz += (double)ri * (double)zi;
+    srr += (double)ri * (double)ri;
+  }
+  srz = block_sum256(srz, sh);
+  srr = block_sum256(srr, sh);
+  if (threadIdx.x == 0) {
+    part_rz[blockIdx.x] = srz;
+    part_rr[blockIdx.x] = srr;
+  }
+}
+
+// rz_new = sum(part_rz), beta = rz_new / rz_old, p = z + beta p; block 0
+// stores rz_new and rr (the scalars are double-buffered by the caller, so no
+// block reads rz_old after it is replaced).
+template <typename T>
+__global__ void __launch_bounds__(256) pcg_p_kernel(T* __restrict__ p, const T* __restrict__ z,
+                                                    const double* __restrict__ part_rz,
+                                                    const double* __restrict__ part_rr,
+                                                    const double* __restrict__ rz_old, double* __restrict__ rz_new,
+                                                    double* __restrict__ rr, long n) {
+  __shared__ double sh[256];
+  const double rzn = sum_partials(part_rz, sh);
+  const T beta = (T)(rzn / *rz_old);
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256) p[i] = z[i] + beta * p[i];
+  if (blockIdx.x == 0) {
+    const double rrn = sum_partials(part_rr, sh);
+    if (threadIdx.x == 0) {
+      *rz_new = rzn;
+      *rr = rrn;
+    }
+  }
 }
 
 template <typename T>
@@ -1054,13 +1157,6 @@ __global__ void axpy64_kernel(double* __restrict__ x, const T* __restrict__ d, l
 
 static int vgrid(long n) { return (int)std::min<long>((n + 255) / 256, 4096); }
 
-#define TETMF_DISPATCH(prec, KERNEL, ...)                                                        \
-  do {                                                                                           \
-    if ((prec) == PREC_F64)                                                                      \
-      hipLaunchKernelGGL(KERNEL<double>, dim3(vgrid(n)), dim3(256), 0, s, __VA_ARGS__);          \
-    else                                                                                         \
-      hipLaunchKernelGGL(KERNEL<float>, dim3(vgrid(n)), dim3(256), 0, s, __VA_ARGS__);           \
-  } while (0)
 
 hipError_t vec_fill(int prec, void* x, double value, int64_t n, hipStream_t s) {
   if (prec == PREC_F64)
@@ -1102,35 +1198,39 @@ hipError_t vec_sub(const double* b, const double* a, double* r, int64_t n, hipSt
   return hipGetLastError();
 }
 
-hipError_t pcg_update_xr(int prec, void* x, void* r, const void* p, const void* q, const double* rz, const double* pq,
-                         int64_t n, hipStream_t s) {
+hipError_t pcg_init(int prec, const void* rhs, const void* dinv, void* x, void* r, void* z, void* p, double* part,
+                    double* rz, double* rr, int64_t n, hipStream_t s) {
   if (prec == PREC_F64)
-    hipLaunchKernelGGL(update_xr<double>, dim3(vgrid(n)), dim3(256), 0, s, (double*)x, (double*)r, (const double*)p,
-                       (const double*)q, rz, pq, (long)n);
+    hipLaunchKernelGGL(pcg_init_kernel<double>, dim3(kVecBlocks), dim3(256), 0, s, (const double*)rhs,
+                       (const double*)dinv, (double*)x, (double*)r, (double*)z, (double*)p, part + kVecBlocks,
+                       part + 2 * kVecBlocks, (long)n);
   else
-    hipLaunchKernelGGL(update_xr<float>, dim3(vgrid(n)), dim3(256), 0, s, (float*)x, (float*)r, (const float*)p,
-                       (const float*)q, rz, pq, (long)n);
+    hipLaunchKernelGGL(pcg_init_kernel<float>, dim3(kVecBlocks), dim3(256), 0, s, (const float*)rhs,
+                       (const float*)dinv, (float*)x, (float*)r, (float*)z, (float*)p, part + kVecBlocks,
+                       part + 2 * kVecBlocks, (long)n);
+  hipLaunchKernelGGL(pcg_scalars_kernel, dim3(1), dim3(256), 0, s, part + kVecBlocks, part + 2 * kVecBlocks, rz, rr);
   return hipGetLastError();
 }
 
-hipError_t pcg_precond(int prec, void* z, const void* r, const void* dinv, int64_t n, hipStream_t s) {
-  if (prec == PREC_F64)
-    hipLaunchKernelGGL(precond_kernel<double>, dim3(vgrid(n)), dim3(256), 0, s, (double*)z, (const double*)r,
-                       (const double*)dinv, (long)n);
-  else
-    hipLaunchKernelGGL(precond_kernel<float>, dim3(vgrid(n)), dim3(256), 0, s, (float*)z, (const float*)r,
-                       (const float*)dinv, (long)n);
-  return hipGetLastError();
-}
-
-hipError_t pcg_update_p(int prec, void* p, const void* z, const double* rz_new, const double* rz_old, int64_t n,
-                        hipStream_t s) {
-  if (prec == PREC_F64)
-    hipLaunchKernelGGL(update_p<double>, dim3(vgrid(n)), dim3(256), 0, s, (double*)p, (const double*)z, rz_new, rz_old,
-                       (long)n);
-  else
-    hipLaunchKernelGGL(update_p<float>, dim3(vgrid(n)), dim3(256), 0, s, (float*)p, (const float*)z, rz_new, rz_old,
-                       (long)n);
+hipError_t pcg_iteration(int prec, void* x, void* r, void* z, void* p, const void* q, const void* dinv, double* part,
+                         const double* rz_old, double* rz_new, double* rr, int64_t n, hipStream_t s) {
+  if (prec == PREC_F64) {
+    hipLaunchKernelGGL(pcg_dot_kernel<double>, dim3(kVecBlocks), dim3(256), 0, s, (const double*)p, (const double*)q,
+                       part, (long)n);
+    hipLaunchKernelGGL(pcg_xr_kernel<double>, dim3(kVecBlocks), dim3(256), 0, s, (double*)x, (double*)r, (double*)z,
+                       (const double*)p, (const double*)q, (const double*)dinv, part, rz_old, part + kVecBlocks,
+                       part + 2 * kVecBlocks, (long)n);
+    hipLaunchKernelGGL(pcg_p_kernel<double>, dim3(kVecBlocks), dim3(256), 0, s, (double*)p, (const double*)z,
+                       part + kVecBlocks, part + 2 * kVecBlocks, rz_old, rz_new, rr, (long)n);
+  } else {
+    hipLaunchKernelGGL(pcg_dot_kernel<float>, dim3(kVecBlocks), dim3(256), 0, s, (const float*)p, (const float*)q,
+                       part, (long)n);
+    hipLaunchKernelGGL(pcg_xr_kernel<float>, dim3(kVecBlocks), dim3(256), 0, s, (float*)x, (float*)r, (float*)z,
+                       (const float*)p, (const float*)q, (const float*)dinv, part, rz_old, part + kVecBlocks,
+                       part + 2 * kVecBlocks, (long)n);
+    hipLaunchKernelGGL(pcg_p_kernel<float>, dim3(kVecBlocks), dim3(256), 0, s, (float*)p, (const float*)z,
+                       part + kVecBlocks, part + 2 * kVecBlocks, rz_old, rz_new, rr, (long)n);
+  }
   return hipGetLastError();
 }
 

@@ -1230,39 +1230,30 @@ double read_scalar(const double* d, hipStream_t s) {
   return h;
 }
 
-// Preconditioned conjugate gradients on op (device-resident scalars; one host
-// read of r.z per iteration for the stopping test).  Solves A d = r0 from
-// d = 0; returns iterations.  Vectors are in the op precision; dot products
-// accumulate in FP64.
+// Preconditioned conjugate gradients on op: solves A d = rhs from d = 0 with
+// fused vector kernels and device-resident scalars; the host reads r.r (one
+// synchronisation) every kCheckEvery iterations, so up to kCheckEvery - 1
+// iterations may run past the target.  Vectors are in the op precision; dot
+// products accumulate in FP64.  Returns the iterations run.
+constexpr int kCheckEvery = 4;
+
 int pcg(tetmf_op* op, const void* kappa, const void* rhs, void* xsol, void* r, void* z, void* pv, void* q,
-        const void* dinv, double* scal, double* part, double rtol_abs2, int max_it, hipStream_t s,
-        double* final_rz) {
+        const void* dinv, double* scal, double* part, double rtol_abs2, int max_it, hipStream_t s) {
   const int kp = kernel_prec(op);
   const int64_t n = op->n_dofs;
-  double* rz = scal + 0;
-  double* rz_new = scal + 1;
-  double* pq = scal + 2;
-  double* rr = scal + 3;
-  check_hip(vec_fill(kp, xsol, 0.0, n, s), "fill");
-  check_hip(hipMemcpyAsync(r, rhs, n * op->esize(), hipMemcpyDeviceToDevice, s), "copy");
-  check_hip(pcg_precond(kp, z, r, dinv, n, s), "precond");
-  check_hip(hipMemcpyAsync(pv, z, n * op->esize(), hipMemcpyDeviceToDevice, s), "copy");
-  check_hip(vec_dot(kp, r, z, n, part, rz, s), "dot");
+  double* rz = scal + 0;  // rz[0], rz[1]: double buffer
+  double* rr = scal + 2;
+  check_hip(pcg_init(kp, rhs, dinv, xsol, r, z, pv, part, rz, rr, n, s), "pcg init");
+  if (read_scalar(rr, s) <= rtol_abs2) return 0;
   int it = 0;
-  for (; it < max_it; ++it) {
-    check_hip(vec_dot(kp, r, r, n, part, rr, s), "dot");
-    double h_rr = read_scalar(rr, s);
-    if (h_rr <= rtol_abs2) break;
+  while (it < max_it) {
     int st = run_cg(op, MODE_APPLY, pv, nullptr, kappa, q, nullptr, s);
     if (st) throw Error(st, g_last_error);
-    check_hip(vec_dot(kp, pv, q, n, part, pq, s), "dot");
-    check_hip(pcg_update_xr(kp, xsol, r, pv, q, rz, pq, n, s), "update");
-    check_hip(pcg_precond(kp, z, r, dinv, n, s), "precond");
-    check_hip(vec_dot(kp, r, z, n, part, rz_new, s), "dot");
-    check_hip(pcg_update_p(kp, pv, z, rz_new, rz, n, s), "update p");
-    check_hip(hipMemcpyAsync(rz, rz_new, sizeof(double), hipMemcpyDeviceToDevice, s), "copy");
+    check_hip(pcg_iteration(kp, xsol, r, z, pv, q, dinv, part, rz + (it & 1), rz + ((it + 1) & 1), rr, n, s),
+              "pcg iteration");
+    ++it;
+    if ((it % kCheckEvery == 0 || it == max_it) && read_scalar(rr, s) <= rtol_abs2) break;
   }
-  if (final_rz) *final_rz = read_scalar(rr, s);
   return it;
 }
 
@@ -1351,7 +1342,7 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
       }
       void* qscratch = opi ? (void*)tmp64 : iq;
       const int its = pcg(ow, opi ? kappai : kappa64, rhs, id, ir, iz, ip, qscratch, idinv, scal, part, target,
-                          opts->max_inner, s, nullptr);
+                          opts->max_inner, s);
       inner_total += its;
       check_hip(vec_axpy_f64(x, id, kpi, n, s), "axpy");
     }
