@@ -762,13 +762,11 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
     for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int g = lane >> 4, c16 = lane & 15;
+  const int wave = threadIdx.x >> 6;
   const int ncp = d.ncp, nc = d.n_cell, nf = d.n_face;
   const T* geo = static_cast<const T*>(d.geo);
   const T* fgeo = static_cast<const T*>(d.fgeo);
   const T sigma = (T)d.sigma;
-  T* so = s_out + wave * kTile * NDOF;
   // tiles of this wave: contiguous tile ranges per XCD
   const int ntiles = ncp / kTile;
   const int nx = 8, x = blockIdx.x % nx;
@@ -776,6 +774,11 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
   const int first = (int)((long long)ntiles * x / nx) + (blockIdx.x / nx) * kWaves + wave;
   const int last = (int)((long long)ntiles * (x + 1) / nx);
   for (int tile = first; tile < last; tile += per) {
+    // lane coordinates re-derived per tile (not held across the tile loop)
+    const int tid = phase_tid();
+    const int lane = tid & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    T* so = s_out + (tid >> 6) * kTile * NDOF;
     const int cell0 = tile * kTile;
     const int cell = cell0 + c16;
     const bool valid = cell < nc;
