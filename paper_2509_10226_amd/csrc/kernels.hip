@@ -163,7 +163,8 @@ struct Tile {
   }
 
   // v: DoFs 0..NMF-1 (element r of lane group g is DoF row(g, r));
-  // vv: DoFs 16..NDOF-1, identical in all lanes of a cell column.
+  // vv[g] (lane groups g < NVA): DoF 16 + g of the lane's cell; the other
+  // entries of vv are not meaningful.
   __device__ static inline void integrate(const T* __restrict__ s_tab, const acc_t (&acc)[MT], int g, int c16,
                                           acc_t& v, T (&vv)[NVA > 0 ? NVA : 1]) {
     v = acc_t{0, 0, 0, 0};
@@ -172,7 +173,22 @@ struct Tile {
       const T a = (NMF == 16 || c16 < NMF) ? s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + c16] : T(0);
       v = M::mma(a, acc[s / 4][s % 4], v);
     }
-    if (NVA > 0) {
+    if constexpr (sizeof(T) == 8 && NVA == 4) {
+      // DoFs 16..19 in FP64 on the 4x4x4 (four blocks) matrix-core product:
+      // lane 16 k + 4 b + i supplies A[b][i][k] and B[b][k][i] and receives
+      // D[b][k][i] (i, k < 4; measured on gfx950).  With block b = cells
+      // 4b..4b+3, K = the four lane groups (the item's four points) and
+      // rows = the four DoFs, the B operand is the item register itself and
+      // lane group g receives DoF 16 + g of its cell: no cross-lane sums.
+      T t = T(0);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const T a = s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + 16 + (c16 & 3)];
+        t = __builtin_amdgcn_mfma_f64_4x4x4f64(a, acc[s / 4][s % 4], t, 0, 0, 0);
+      }
+#pragma unroll
+      for (int jj = 0; jj < NVA; ++jj) vv[jj] = t;
+    } else if (NVA > 0) {
       T part[NVA > 0 ? NVA : 1];
 #pragma unroll
       for (int jj = 0; jj < NVA; ++jj) part[jj] = T(0);
