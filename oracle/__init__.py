@@ -19,6 +19,7 @@ Modules
   mesh      geometry, faces, DoF identities, Dirichlet constraints
   assemble  CG/DG assembly, coefficient gradients, load vector, row samples
   exact     exact rational brute force used to pin ``assemble``
+  smoother  Jacobi-preconditioned Chebyshev smoother (Sec. 4.1)
 
 Parity unpinned: nothing — every function here has at least one pin in
 ``tests/test_oracle_*.py`` (closed forms, exact rational arithmetic,
@@ -26,6 +27,7 @@ invariants); see the test docstrings for which pin covers which function.
 """
 from .basis import nodes, eval_basis  # noqa: F401
 from .mesh import Geometry, cg_dofs, find_faces  # noqa: F401
+from .smoother import chebyshev  # noqa: F401
 from .assemble import (  # noqa: F401
     assemble_cg, assemble_dg, cg_kappa_grad, dg_kappa_grad, load_vector, cg_rows, dg_rows,
 )
