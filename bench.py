@@ -327,6 +327,44 @@ def bench_f1(args):
           flush=True)
 
 
+def bench_f4(args):
+    """Jacobi-preconditioned Chebyshev smoothing (degree 5, as in the
+    multigrid of Sec. 4.1) on the solve workload, FP64 and FP32: time per
+    smoother call and per step (one operator application plus the fused
+    vector update), and the Lanczos estimate of lambda_max(D^-1 A)."""
+    import torch
+
+    import paper_2509_10226_amd as tm
+    import synth
+    n = args.n
+    xyz, tets = synth.kuhn_cube_mesh(n, 0.15, 0)
+    qp, qw = synth.tet_rule(6)
+    mesh = tm.Mesh(xyz, tets)
+    res = {}
+    for prec in ("f64", "f32"):
+        op = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet", precision=prec)
+        inv = 1.0 / op.diagonal()
+        t0 = time.perf_counter()
+        lam = op.estimate_lambda_max(inv, n_iter=20)
+        t_est = time.perf_counter() - t0
+        lmax = 1.1 * lam
+        lmin = lmax / 15.0
+        b = op.load_vector()
+        x = torch.zeros_like(b)
+        ms = _time_call(lambda: op.chebyshev(b, inv, 5, lmin, lmax, x=x), args.steps, args.warmup)
+        u = torch.rand(op.n_dofs, dtype=op.dtype, device="cuda")
+        ms_apply = _time_call(lambda: op.apply(u), args.steps, args.warmup)
+        res[prec] = {"ms_per_smoothing": round(ms, 5), "steps": 5, "ms_per_step": round(ms / 5, 5),
+                     "DoFs_per_s_per_step": round(op.n_dofs * 5 / (ms * 1e-3), 1),
+                     "ms_per_apply": round(ms_apply, 5), "lambda_max_estimate": lam,
+                     "estimate_seconds_20_steps": round(t_est, 4)}
+        del op
+    print(json.dumps({"metric": "DoFs/s per Chebyshev-Jacobi smoothing step, CG P3 (degree 5)", "unit": "DoFs/s",
+                      "config": {"workload": f"CG P3 Poisson, Dirichlet, kappa=1, {n}^3x6 Kuhn tets, 24-point rule; "
+                                             "interval [lambda_max/15, 1.1 lambda_max]"},
+                      "variants": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,8 +372,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=64, help="cubes per axis (64 = the measured workload)")
     ap.add_argument("--precisions", default="f64,f32,bf16in")
-    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5", "order", "f1"],
-                    help="c3 (default): the measured workload; c2/c4/c5/order/f1: secondary measurements, "
+    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5", "order", "f1", "f4"],
+                    help="c3 (default): the measured workload; c2/c4/c5/order/f1/f4: secondary measurements, "
                          "each printed as its own JSON line")
     ap.add_argument("--order-variant", default="all",
                     choices=["all", "native_locality", "shuffled_locality", "shuffled_as_given"])
@@ -353,7 +391,8 @@ def main():
         copy_calibration()
         return
     if args.config != "c3":
-        {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "order": bench_order, "f1": bench_f1}[args.config](args)
+        {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "order": bench_order, "f1": bench_f1,
+         "f4": bench_f4}[args.config](args)
         return
     dev = torch.device("cuda", 0)
     xyz, tets, qp, qw, kap = build_workload(args.n)

@@ -201,6 +201,40 @@ int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* op_inner, const v
                 const double* b, double* x, const tetmf_solve_opts* opts, tetmf_solve_stats* stats,
                 void* stream);
 
+/* Chebyshev iteration preconditioned by the point Jacobi diagonal: the
+ * smoother of the multigrid V-cycle of Sec. 4.1 (five pre- and five
+ * post-smoothing steps per level there, run in single precision).  With
+ * D = diag(A), theta = (lambda_max + lambda_min) / 2 and
+ * delta = (lambda_max - lambda_min) / 2:
+ *   r_0 = b - A x_0 (b when zero_guess), d_0 = D^-1 r_0 / theta,
+ *   x_1 = x_0 + d_0, rho_0 = delta / theta, and for k = 1 .. degree - 1:
+ *   r_k = b - A x_k, rho_k = 1 / (2 theta / delta - rho_{k-1}),
+ *   d_k = rho_k rho_{k-1} d_{k-1} + (2 rho_k / delta) D^-1 r_k,
+ *   x_{k+1} = x_k + d_k.
+ * The error x* - x is multiplied by p(D^-1 A) with
+ * p(t) = T_degree((theta - t) / delta) / T_degree(theta / delta); one
+ * operator application per step (degree - 1 with zero_guess).
+ *  inv_diag: device [n_dofs], 1 / tetmf_diagonal (constrained entries 1).
+ *  b: device [n_dofs]; x: device [n_dofs], x_0 on entry unless zero_guess,
+ *  the smoothed vector on exit.  All in the op precision (FP32 for BF16IN).
+ *  kappa_cell as for tetmf_apply.
+ *  degree >= 1, 0 <= lambda_min < lambda_max (INVALID_ARGUMENT otherwise);
+ *  x may not alias b or inv_diag (ALIAS).  CG only (UNSUPPORTED for DG).
+ *  Two work vectors are allocated by the op on the first call and kept.
+ *  Asynchronous on the stream. */
+int tetmf_chebyshev(tetmf_op* op, const void* kappa_cell, const void* inv_diag, const void* b, void* x,
+                    int degree, double lambda_min, double lambda_max, int zero_guess, void* stream);
+
+/* Estimate of the largest eigenvalue of D^-1 A (D = diag(A)), the upper end
+ * of the smoother's interval: n_iter steps of Jacobi-preconditioned
+ * conjugate gradients on A y = r_0 from a fixed pseudo-random r_0, and the
+ * largest eigenvalue of the Lanczos tridiagonal matrix formed from their
+ * step lengths (a lower bound of the true value that converges from below;
+ * smoothers commonly scale it by 1.1-1.2).  n_iter in 1..500.  inv_diag as
+ * for tetmf_chebyshev.  Allocates and frees temporaries; synchronises. */
+int tetmf_estimate_lambda_max(tetmf_op* op, const void* kappa_cell, const void* inv_diag, int n_iter,
+                              double* lambda_max, void* stream);
+
 /* Measurement aid.  While enabled, every launch of the op's main kernel (the
  * cell kernel of apply, backward, diagonal and load vector; the
  * cell-and-face kernel for DG) carries a HIP event pair that takes the start

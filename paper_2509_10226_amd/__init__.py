@@ -86,6 +86,11 @@ _SIGS = {
     "tetmf_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(SolveOpts),
                                    ctypes.POINTER(SolveStats), ctypes.c_void_p]),
+    "tetmf_chebyshev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_void_p]),
+    "tetmf_estimate_lambda_max": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                                 ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]),
     "tetmf_op_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "tetmf_op_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int64)]),
@@ -332,6 +337,29 @@ class Operator:
             ctypes.byref(o), ctypes.byref(st), _stream()))
         stats = {k: getattr(st, k) for k, _ in SolveStats._fields_}
         return x, stats, status == 0
+
+    def chebyshev(self, b, inv_diag, degree, lambda_min, lambda_max, x=None, kappa=None):
+        """Jacobi-preconditioned Chebyshev smoothing of A x = b (see
+        tetmf_chebyshev); x None starts from zero.  Returns x (updated in place
+        when given)."""
+        torch = _torch()
+        zero = x is None
+        if zero:
+            x = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
+        _check(lib().tetmf_chebyshev(self._h, _ptr(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
+                                     _ptr(inv_diag, self.dtype, self.n_dofs, "inv_diag"),
+                                     _ptr(b, self.dtype, self.n_dofs, "b"), _ptr(x, self.dtype, self.n_dofs, "x"),
+                                     int(degree), float(lambda_min), float(lambda_max), 1 if zero else 0, _stream()))
+        return x
+
+    def estimate_lambda_max(self, inv_diag, n_iter=20, kappa=None):
+        """Lanczos estimate of the largest eigenvalue of D^-1 A (see
+        tetmf_estimate_lambda_max)."""
+        lam = ctypes.c_double()
+        _check(lib().tetmf_estimate_lambda_max(self._h, _ptr(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
+                                               _ptr(inv_diag, self.dtype, self.n_dofs, "inv_diag"), int(n_iter),
+                                               ctypes.byref(lam), _stream()))
+        return lam.value
 
 
 def _profile_methods():

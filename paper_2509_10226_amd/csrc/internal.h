@@ -93,9 +93,16 @@ hipError_t pcg_init(int prec, const void* rhs, const void* dinv, void* x, void* 
                     double* rz, double* rr, int64_t n, hipStream_t s);
 // One iteration after q = A p: alpha = rz_old / p.q, x += alpha p,
 // r -= alpha q, z = dinv r, *rz_new = r.z, beta = rz_new / rz_old,
-// p = z + beta p, *rr = r.r.  rz_old and rz_new must be distinct.
+// p = z + beta p, *rr = r.r, and *pq_out = p.q when pq_out is not NULL.
+// rz_old and rz_new must be distinct.
 hipError_t pcg_iteration(int prec, void* x, void* r, void* z, void* p, const void* q, const void* dinv, double* part,
-                         const double* rz_old, double* rz_new, double* rr, int64_t n, hipStream_t s);
+                         const double* rz_old, double* rz_new, double* rr, double* pq_out, int64_t n, hipStream_t s);
+// One Chebyshev-Jacobi step (see tetmf_chebyshev): r = b - ax (ax NULL: r = b),
+// d = cd d + cr dinv r (d not read unless d_read), x = (x_read ? x : 0) + d.
+hipError_t cheb_step(int prec, const void* b, const void* ax, const void* dinv, void* d, void* x, double cd,
+                     double cr, int d_read, int x_read, int64_t n, hipStream_t s);
+// x_i in [-1, 1) from a fixed integer hash of i.
+hipError_t vec_hash_fill(int prec, void* x, int64_t n, hipStream_t s);
 hipError_t vec_recip(int prec, void* d, int64_t n, hipStream_t s);
 hipError_t vec_axpy_f64(double* x, const void* d, int prec_d, int64_t n, hipStream_t s);
 

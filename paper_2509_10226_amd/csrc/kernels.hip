@@ -1121,9 +1121,12 @@ __global__ void __launch_bounds__(256) pcg_xr_kernel(T* __restrict__ x, T* __res
                                                      const T* __restrict__ p, const T* __restrict__ q,
                                                      const T* __restrict__ dinv, const double* __restrict__ part_pq,
                                                      const double* __restrict__ rz, double* __restrict__ part_rz,
-                                                     double* __restrict__ part_rr, long n) {
+                                                     double* __restrict__ part_rr, double* __restrict__ pq_out,
+                                                     long n) {
   __shared__ double sh[256];
-  const T a = (T)(*rz / sum_partials(part_pq, sh));
+  const double pq = sum_partials(part_pq, sh);
+  if (pq_out && blockIdx.x == 0 && threadIdx.x == 0) *pq_out = pq;
+  const T a = (T)(*rz / pq);
   double srz = 0, srr = 0;
   for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256) {
     x[i] += a * p[i];
@@ -1161,6 +1164,34 @@ __global__ void __launch_bounds__(256) pcg_p_kernel(T* __restrict__ p, const T* 
       *rz_new = rzn;
       *rr = rrn;
     }
+  }
+}
+
+// One Chebyshev-Jacobi step: r = b - (ax ? ax : 0), d = cd d + cr dinv r
+// (d not read when cd_read is 0), x = (x_read ? x : 0) + d.
+template <typename T>
+__global__ void __launch_bounds__(256) cheb_step_kernel(const T* __restrict__ b, const T* __restrict__ ax,
+                                                        const T* __restrict__ dinv, T* __restrict__ d,
+                                                        T* __restrict__ x, T cd, T cr, int d_read, int x_read,
+                                                        long n) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    const T r = ax ? b[i] - ax[i] : b[i];
+    const T di = (d_read ? cd * d[i] : T(0)) + cr * (dinv[i] * r);
+    d[i] = di;
+    x[i] = (x_read ? x[i] : T(0)) + di;
+  }
+}
+
+// x_i in [-1, 1) from the SplitMix64 output function (Steele, Lea and Flood,
+// 2014) applied to i: a reproducible start vector.
+template <typename T>
+__global__ void hash_fill_kernel(T* __restrict__ x, long n) {
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+    uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    x[i] = (T)((double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0);
   }
 }
 
@@ -1232,13 +1263,13 @@ hipError_t pcg_init(int prec, const void* rhs, const void* dinv, void* x, void* 
 }
 
 hipError_t pcg_iteration(int prec, void* x, void* r, void* z, void* p, const void* q, const void* dinv, double* part,
-                         const double* rz_old, double* rz_new, double* rr, int64_t n, hipStream_t s) {
+                         const double* rz_old, double* rz_new, double* rr, double* pq_out, int64_t n, hipStream_t s) {
   if (prec == PREC_F64) {
     hipLaunchKernelGGL(pcg_dot_kernel<double>, dim3(kVecBlocks), dim3(256), 0, s, (const double*)p, (const double*)q,
                        part, (long)n);
     hipLaunchKernelGGL(pcg_xr_kernel<double>, dim3(kVecBlocks), dim3(256), 0, s, (double*)x, (double*)r, (double*)z,
                        (const double*)p, (const double*)q, (const double*)dinv, part, rz_old, part + kVecBlocks,
-                       part + 2 * kVecBlocks, (long)n);
+                       part + 2 * kVecBlocks, pq_out, (long)n);
     hipLaunchKernelGGL(pcg_p_kernel<double>, dim3(kVecBlocks), dim3(256), 0, s, (double*)p, (const double*)z,
                        part + kVecBlocks, part + 2 * kVecBlocks, rz_old, rz_new, rr, (long)n);
   } else {
@@ -1246,10 +1277,29 @@ hipError_t pcg_iteration(int prec, void* x, void* r, void* z, void* p, const voi
                        part, (long)n);
     hipLaunchKernelGGL(pcg_xr_kernel<float>, dim3(kVecBlocks), dim3(256), 0, s, (float*)x, (float*)r, (float*)z,
                        (const float*)p, (const float*)q, (const float*)dinv, part, rz_old, part + kVecBlocks,
-                       part + 2 * kVecBlocks, (long)n);
+                       part + 2 * kVecBlocks, pq_out, (long)n);
     hipLaunchKernelGGL(pcg_p_kernel<float>, dim3(kVecBlocks), dim3(256), 0, s, (float*)p, (const float*)z,
                        part + kVecBlocks, part + 2 * kVecBlocks, rz_old, rz_new, rr, (long)n);
   }
+  return hipGetLastError();
+}
+
+hipError_t cheb_step(int prec, const void* b, const void* ax, const void* dinv, void* d, void* x, double cd,
+                     double cr, int d_read, int x_read, int64_t n, hipStream_t s) {
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(cheb_step_kernel<double>, dim3(vgrid(n)), dim3(256), 0, s, (const double*)b, (const double*)ax,
+                       (const double*)dinv, (double*)d, (double*)x, cd, cr, d_read, x_read, (long)n);
+  else
+    hipLaunchKernelGGL(cheb_step_kernel<float>, dim3(vgrid(n)), dim3(256), 0, s, (const float*)b, (const float*)ax,
+                       (const float*)dinv, (float*)d, (float*)x, (float)cd, (float)cr, d_read, x_read, (long)n);
+  return hipGetLastError();
+}
+
+hipError_t vec_hash_fill(int prec, void* x, int64_t n, hipStream_t s) {
+  if (prec == PREC_F64)
+    hipLaunchKernelGGL(hash_fill_kernel<double>, dim3(vgrid(n)), dim3(256), 0, s, (double*)x, (long)n);
+  else
+    hipLaunchKernelGGL(hash_fill_kernel<float>, dim3(vgrid(n)), dim3(256), 0, s, (float*)x, (long)n);
   return hipGetLastError();
 }
 

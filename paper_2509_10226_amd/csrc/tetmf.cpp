@@ -364,8 +364,9 @@ struct tetmf_op {
   double flops = 0, bytes = 0;
   const tetmf_mesh* mesh_tag = nullptr;
   int64_t mesh_nc = 0, mesh_nv = 0;
-  // solver scratch (allocated on first solve)
+  // solver scratch (allocated on first solve) and smoother scratch (first smoothing)
   std::vector<DevBuf> solve_bufs;
+  std::vector<DevBuf> cheb_bufs;
   // kernel timing (tetmf_op_profile)
   bool profiling = false;
   std::vector<hipEvent_t> events;  // pairs
@@ -384,12 +385,13 @@ struct tetmf_op {
   }
 
   ~tetmf_op() {
-    if (bufs.empty() && solve_bufs.empty() && events.empty()) return;
+    if (bufs.empty() && solve_bufs.empty() && cheb_bufs.empty() && events.empty()) return;
     int cur = 0;
     (void)hipGetDevice(&cur);
     (void)hipSetDevice(device);
     for (auto& b : bufs) (void)hipFree(b.p);
     for (auto& b : solve_bufs) (void)hipFree(b.p);
+    for (auto& b : cheb_bufs) (void)hipFree(b.p);
     for (auto e : events) (void)hipEventDestroy(e);
     (void)hipSetDevice(cur);
   }
@@ -1249,7 +1251,7 @@ int pcg(tetmf_op* op, const void* kappa, const void* rhs, void* xsol, void* r, v
   while (it < max_it) {
     int st = run_cg(op, MODE_APPLY, pv, nullptr, kappa, q, nullptr, s);
     if (st) throw Error(st, g_last_error);
-    check_hip(pcg_iteration(kp, xsol, r, z, pv, q, dinv, part, rz + (it & 1), rz + ((it + 1) & 1), rr, n, s),
+    check_hip(pcg_iteration(kp, xsol, r, z, pv, q, dinv, part, rz + (it & 1), rz + ((it + 1) & 1), rr, nullptr, n, s),
               "pcg iteration");
     ++it;
     if ((it % kCheckEvery == 0 || it == max_it) && read_scalar(rr, s) <= rtol_abs2) break;
@@ -1355,6 +1357,150 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
     }
     if (status != TETMF_OK) g_last_error = "tetmf_solve: iteration caps reached";
     return status;
+  });
+}
+
+extern "C" int tetmf_chebyshev(tetmf_op* op, const void* kappa, const void* inv_diag, const void* b, void* x,
+                               int degree, double lambda_min, double lambda_max, int zero_guess, void* stream) {
+  return guarded([&]() -> int {
+    if (!op || !inv_diag || !b || !x) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_chebyshev: NULL argument");
+    if (op->kind != TETMF_CG) return fail(TETMF_ERR_UNSUPPORTED, "tetmf_chebyshev: only CG operators");
+    if (degree < 1 || !std::isfinite(lambda_min) || !std::isfinite(lambda_max) || lambda_min < 0 ||
+        !(lambda_min < lambda_max))
+      return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_chebyshev: need degree >= 1 and 0 <= lambda_min < lambda_max");
+    if (x == b || x == inv_diag) return fail(TETMF_ERR_ALIAS, "tetmf_chebyshev: x aliases b or inv_diag");
+    DeviceScope dsc(op->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = op->n_dofs;
+    if (op->cheb_bufs.empty()) {
+      for (int i = 0; i < 2; ++i) {
+        void* p = nullptr;
+        check_hip(hipMalloc(&p, std::max<size_t>((size_t)n * op->esize(), 16)), "hipMalloc");
+        op->cheb_bufs.push_back({p, (size_t)n * op->esize()});
+      }
+    }
+    void* d = op->cheb_bufs[0].p;
+    void* ax = op->cheb_bufs[1].p;
+    const int kp = kernel_prec(op);
+    const double theta = 0.5 * (lambda_max + lambda_min), delta = 0.5 * (lambda_max - lambda_min);
+    if (zero_guess) {
+      check_hip(cheb_step(kp, b, nullptr, inv_diag, d, x, 0.0, 1.0 / theta, 0, 0, n, s), "chebyshev step");
+    } else {
+      int st = run_cg(op, MODE_APPLY, x, nullptr, kappa, ax, nullptr, s);
+      if (st) return st;
+      check_hip(cheb_step(kp, b, ax, inv_diag, d, x, 0.0, 1.0 / theta, 0, 1, n, s), "chebyshev step");
+    }
+    double rho_prev = delta / theta;
+    for (int k = 1; k < degree; ++k) {
+      int st = run_cg(op, MODE_APPLY, x, nullptr, kappa, ax, nullptr, s);
+      if (st) return st;
+      const double rho = 1.0 / (2.0 * theta / delta - rho_prev);
+      check_hip(cheb_step(kp, b, ax, inv_diag, d, x, rho * rho_prev, 2.0 * rho / delta, 1, 1, n, s),
+                "chebyshev step");
+      rho_prev = rho;
+    }
+    return TETMF_OK;
+  });
+}
+
+namespace {
+
+// Number of eigenvalues below t of the symmetric tridiagonal matrix (diag a,
+// off-diagonal b) by the Sturm sequence of its LDL^T pivots.
+int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double t) {
+  int count = 0;
+  double q = 1.0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double off = i == 0 ? 0.0 : b[i - 1] * b[i - 1];
+    q = a[i] - t - (i == 0 ? 0.0 : off / q);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0) ++count;
+  }
+  return count;
+}
+
+double tridiag_lambda_max(const std::vector<double>& a, const std::vector<double>& b) {
+  double lo = a[0], hi = a[0];
+  for (size_t i = 0; i < a.size(); ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < a.size() ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  const int k = (int)a.size();
+  for (int it = 0; it < 200 && hi - lo > 1e-14 * std::max(1.0, std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (sturm_count(a, b, mid) < k)
+      lo = mid;  // the largest eigenvalue is above mid
+    else
+      hi = mid;
+  }
+  return hi;
+}
+
+}  // namespace
+
+extern "C" int tetmf_estimate_lambda_max(tetmf_op* op, const void* kappa, const void* inv_diag, int n_iter,
+                                         double* lambda_max, void* stream) {
+  return guarded([&]() -> int {
+    if (!op || !inv_diag || !lambda_max)
+      return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_estimate_lambda_max: NULL argument");
+    if (op->kind != TETMF_CG) return fail(TETMF_ERR_UNSUPPORTED, "tetmf_estimate_lambda_max: only CG operators");
+    if (n_iter < 1 || n_iter > 500)
+      return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_estimate_lambda_max: n_iter must be in 1..500");
+    DeviceScope dsc(op->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = op->n_dofs;
+    const size_t vb = std::max<size_t>((size_t)n * op->esize(), 16);
+    // temporaries, freed on every exit path
+    struct Tmp {
+      std::vector<void*> v;
+      ~Tmp() {
+        for (void* p : v) (void)hipFree(p);
+      }
+    } tmp;
+    auto al = [&](size_t bytes) {
+      void* p = nullptr;
+      check_hip(hipMalloc(&p, bytes), "hipMalloc");
+      tmp.v.push_back(p);
+      return p;
+    };
+    void* rhs = al(vb);
+    void* xv = al(vb);
+    void* r = al(vb);
+    void* z = al(vb);
+    void* pv = al(vb);
+    void* q = al(vb);
+    double* scal = (double*)al(8 * sizeof(double));
+    double* part = (double*)al(3 * 512 * sizeof(double));
+    const int kp = kernel_prec(op);
+    check_hip(vec_hash_fill(kp, rhs, n, s), "fill");
+    check_hip(pcg_init(kp, rhs, inv_diag, xv, r, z, pv, part, scal + 0, scal + 2, n, s), "pcg init");
+    double rz_old = read_scalar(scal + 0, s);
+    std::vector<double> alpha, beta;
+    for (int it = 0; it < n_iter && rz_old > 0 && std::isfinite(rz_old); ++it) {
+      int st = run_cg(op, MODE_APPLY, pv, nullptr, kappa, q, nullptr, s);
+      if (st) return st;
+      check_hip(pcg_iteration(kp, xv, r, z, pv, q, inv_diag, part, scal + (it & 1), scal + ((it + 1) & 1), scal + 2,
+                              scal + 3, n, s),
+                "pcg iteration");
+      const double pq = read_scalar(scal + 3, s);
+      const double rz_new = read_scalar(scal + ((it + 1) & 1), s);
+      if (!(pq > 0) || !std::isfinite(pq)) break;
+      alpha.push_back(rz_old / pq);
+      beta.push_back(rz_new / rz_old);
+      rz_old = rz_new;
+    }
+    check_hip(hipStreamSynchronize(s), "sync");
+    if (alpha.empty()) return fail(TETMF_ERR_DEVICE, "tetmf_estimate_lambda_max: no conjugate-gradient step");
+    // Lanczos tridiagonal matrix of D^-1 A from the conjugate-gradient coefficients
+    const size_t k = alpha.size();
+    std::vector<double> a(k), b(k > 0 ? k - 1 : 0);
+    for (size_t j = 0; j < k; ++j) {
+      a[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+      if (j + 1 < k) b[j] = std::sqrt(beta[j]) / alpha[j];
+    }
+    *lambda_max = tridiag_lambda_max(a, b);
+    return TETMF_OK;
   });
 }
 

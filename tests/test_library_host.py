@@ -112,3 +112,10 @@ def test_host_setup_rejects_unsupported(L):
     with pytest.raises(L.TetmfError) as e:
         L.check_setup(m, 3, synth.tet_rule(6), kind="dg")  # face rule missing
     assert e.value.status == -1
+
+
+def test_smoother_argument_errors(L):
+    lib = L.lib()
+    lam = ctypes.c_double()
+    assert lib.tetmf_chebyshev(None, None, None, None, None, 5, 0.1, 2.0, 1, None) == -1
+    assert lib.tetmf_estimate_lambda_max(None, None, None, 10, ctypes.byref(lam), None) == -1
