@@ -158,16 +158,23 @@ def copy_calibration(mib=1024, reps=3):
     print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "reps": reps}), flush=True)
 
 
-def _time_call(fn, steps, warmup):
+def _time_call(fn, steps, warmup, op=None):
+    """Milliseconds per call over `steps` timed calls after `warmup` calls;
+    with op, its kernel profiling covers exactly the timed calls."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if op is not None:
+        op.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if op is not None:
+        op.profile(False)
+    return ms
 
 
 def bench_c2(args):
@@ -188,9 +195,7 @@ def bench_c2(args):
     klf = torch.from_numpy(kf.T.copy()).cuda()
     u = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda") * 2 - 1
     out = torch.empty_like(u)
-    op.profile(True)
-    ms = _time_call(lambda: op.apply(u, klc, klf, out=out), args.steps, args.warmup)
-    op.profile(False)
+    ms = _time_call(lambda: op.apply(u, klc, klf, out=out), args.steps, args.warmup, op)
     kms, nl = op.profile_read()
     kms /= nl
     print(json.dumps({"metric": "DoFs/s per SIPG operator apply, P3, FP64", "value": round(op.n_dofs / (ms * 1e-3), 1),
@@ -214,13 +219,9 @@ def bench_c4(args):
     kl = op.cell_data_to_library(torch.from_numpy(kap).cuda())
     u = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda") * 2 - 1
     g = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda") * 2 - 1
-    op.profile(True)
-    ms_f = _time_call(lambda: op.apply(u, kl), args.steps, args.warmup)
-    op.profile(False)
+    ms_f = _time_call(lambda: op.apply(u, kl), args.steps, args.warmup, op)
     kf, nf = op.profile_read()
-    op.profile(True)
-    ms_b = _time_call(lambda: op.backward(u, g, kl), args.steps, args.warmup)
-    op.profile(False)
+    ms_b = _time_call(lambda: op.backward(u, g, kl), args.steps, args.warmup, op)
     kb, nb = op.profile_read()
     print(json.dumps({"metric": "DoFs/s per apply and per backward (du, dkappa), CG P2 Helmholtz, FP64",
                       "value": round(op.n_dofs / (ms_f * 1e-3), 1), "unit": "DoFs/s",

@@ -666,9 +666,10 @@ hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
-  // With ev, the events take the start and end timestamps of this dispatch
-  // itself, so their elapsed time is the kernel's duration alone.
-  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
+  // With ev: ev[0] is a marker recorded after the preceding work on the
+  // stream has finished, ev[1] takes the end timestamp of this dispatch.
+  if (ev) (void)hipEventRecord(ev[0], s);
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, nullptr, ev ? ev[1] : nullptr, 0u, d,
                         (const T*)u, (const T*)g, (const T*)kappa, (T*)out, (T*)dk);
   e = hipGetLastError();
   if (e != hipSuccess || out == nullptr) return e;
@@ -683,7 +684,8 @@ hipError_t launch_cg_vec(const CGDev& d, const void* kappa, void* out, hipStream
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
-  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
+  if (ev) (void)hipEventRecord(ev[0], s);
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, nullptr, ev ? ev[1] : nullptr, 0u, d,
                         (const T*)kappa, (T*)out);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -936,7 +938,8 @@ hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, (ntiles + kWaves - 1) / kWaves);
-  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
+  if (ev) (void)hipEventRecord(ev[0], s);
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, nullptr, ev ? ev[1] : nullptr, 0u, d,
                         (const T*)u, (const T*)kc, (const T*)kf, (T*)v);
   e = hipGetLastError();
   return e;
