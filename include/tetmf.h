@@ -119,7 +119,10 @@ int tetmf_mesh_faces(const tetmf_mesh* mesh, int64_t* n_face, int64_t* n_interio
  * J^{-T} computed in FP64 and rounded to the op precision, basis tables,
  * face data.  Allocates device memory (OUT_OF_MEMORY on failure).
  * UNSUPPORTED for a (degree, n_q, n_qf, precision, kind) combination with no
- * compiled kernel.  The mesh may be destroyed afterwards. */
+ * compiled kernel, and for meshes beyond the kernels' 32-bit indexing
+ * (n_dof_cell x n_cell, rounded up to whole 256-cell blocks for CG and to
+ * 16-cell tiles for DG, must stay below 2^31: about 107 million cells at
+ * P3).  The mesh may be destroyed afterwards. */
 int tetmf_op_create(const tetmf_mesh* mesh, const tetmf_op_desc* desc, tetmf_op** out);
 void tetmf_op_destroy(tetmf_op* op);
 int tetmf_op_info(const tetmf_op* op, tetmf_info* info);

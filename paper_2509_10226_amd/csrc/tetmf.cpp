@@ -669,6 +669,11 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
   const int64_t nb = (nc + kBlockCells - 1) / kBlockCells;
   op->n_blocks = nb;
   op->ncp = nb * kBlockCells;
+  // the kernels address the [n_dof][ncp] index arrays with 32-bit integers
+  if ((int64_t)nd * op->ncp > INT32_MAX)
+    throw Error(TETMF_ERR_UNSUPPORTED, "mesh too large for one operator: at most " +
+                                           std::to_string(INT32_MAX / nd / kBlockCells * kBlockCells) +
+                                           " cells at this degree (32-bit indexing)");
   std::vector<int32_t> bmin(ntmp, INT32_MAX), bmax(ntmp, -1);
   for (int64_t i = 0; i < nc; ++i) {
     int32_t b = (int32_t)(i / kBlockCells);
@@ -830,7 +835,8 @@ void setup_dg(tetmf_op* op, const tetmf_mesh& m, bool device) {
   op->ncp = ((nc + kTile - 1) / kTile) * kTile;
   op->n_dofs = nc * nd;
   op->n_free = op->n_dofs;
-  if (op->n_dofs > INT32_MAX) throw Error(TETMF_ERR_UNSUPPORTED, "more than 2^31 DoFs");
+  // DoF and per-cell array indices are 32-bit in the kernels
+  if ((int64_t)nd * op->ncp > INT32_MAX) throw Error(TETMF_ERR_UNSUPPORTED, "more than 2^31 DoFs");
   const auto& perm = op->cell_perm;
   const auto& u2l = op->user_to_lib;
   op->dof_xyz.assign((size_t)3 * op->n_dofs, 0.0);
