@@ -349,6 +349,14 @@ static int persistent_grid(const void* kern, size_t lds, int work) {
 //    shared DoFs become partial sums that cg_combine adds in block order.
 // Every sum has a fixed order, so the result is bitwise reproducible.
 
+// Load base[off / sizeof(X)] with a wave-uniform 64-bit base and a per-lane
+// 32-bit byte offset, the form the global loads with a scalar base address
+// take (no 64-bit address arithmetic per lane).
+template <typename X>
+__device__ inline X load_at(const X* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // Thread index hidden from loop-invariant code motion: values derived from it
 // inside a phase are not kept live across the other phases of the block loop
 // (the compute phase needs every register for the matrix-core tiles).
@@ -479,18 +487,26 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
       const int cl = (wave + tt * kWaves) * kTile + c16;
       const int cell = b * kBlockCells + cl;
       const bool valid = cell < nc;
-      const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
-      const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
-      const T adet = (C == 4) ? geo[6 * ncp + cell] : T(0);
-      // coefficient at this lane's points, loaded from a clamped (always
-      // valid) address and masked afterwards
+      // per-cell arrays: row base (uniform) + 32-bit lane offset
+      const uint32_t coff = (uint32_t)cell * (uint32_t)sizeof(T);
+      const T G0 = load_at(geo, coff), G1 = load_at(geo + ncp, coff), G2 = load_at(geo + 2 * (long)ncp, coff);
+      const T G3 = load_at(geo + 3 * (long)ncp, coff), G4 = load_at(geo + 4 * (long)ncp, coff);
+      const T G5 = load_at(geo + 5 * (long)ncp, coff);
+      const T adet = (C == 4) ? load_at(geo + 6 * (long)ncp, coff) : T(0);
+      // coefficient at this lane's points q = g + 4k (row q of [NQ][nc]),
+      // from a clamped (always valid) address and masked afterwards
       T kq[KP];
       if (kappa) {
         const int cc = valid ? cell : nc - 1;
+        const uint32_t kof = ((uint32_t)g * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T);
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-          const int q = g + 4 * k;
-          kq[k] = kappa[(long)(q < NQ ? q : NQ - 1) * nc + cc];
+          if (4 * k + 3 < NQ) {
+            kq[k] = load_at(kappa + (long)(4 * k) * nc, kof);
+          } else {
+            const int q = min(g + 4 * k, NQ - 1);
+            kq[k] = load_at(kappa, ((uint32_t)q * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T));
+          }
         }
       } else {
 #pragma unroll
@@ -498,11 +514,16 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
       }
       uint16_t pv[4 + TL::NVA];
       if (write_out) {
+        // row(g, r) = row(g, 0) + row(0, r): lane part and uniform part
+        const uint32_t pof = ((uint32_t)M::row(g, 0) * (uint32_t)ncp + (uint32_t)cell) * 2u;
 #pragma unroll
         // rows beyond the cell's DoFs (fewer than 16 at p <= 2) have no slot
         for (int r = 0; r < 4; ++r)
-          pv[r] = (TL::NMF == 16 || M::row(g, r) < TL::NMF) ? d.pos[M::row(g, r) * ncp + cell] : uint16_t(0);
-        if (TL::NVA > 0) pv[4] = d.pos[(16 + min(g, TL::NVA - 1)) * ncp + cell];
+          pv[r] = (TL::NMF == 16 || M::row(g, r) < TL::NMF) ? load_at(d.pos + (long)M::row(0, r) * ncp, pof)
+                                                             : uint16_t(0);
+        if (TL::NVA > 0)
+          pv[4] = load_at(d.pos + 16 * (long)ncp,
+                          ((uint32_t)min(g, TL::NVA - 1) * (uint32_t)ncp + (uint32_t)cell) * 2u);
       }
       T ub[NB];
       T gb[BWD ? NB : 1];
