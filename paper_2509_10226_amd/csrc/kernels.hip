@@ -118,19 +118,24 @@ struct Tile {
   static constexpr int NPT = 4 * KP;
   static constexpr int NMF = NDOF < 16 ? NDOF : 16;
   static constexpr int NVA = NDOF - NMF;
-  static constexpr int TAB = NPT * C * NDP;
+  // table rows reach the points of every item of the MT interpolation tiles
+  // (items NS..4 MT - 1 of the last tile read zero rows, so no lane needs a
+  // predicated load)
+  static constexpr int NPTP = 4 * ((4 * MT - 1) / C + 1);
+  static constexpr int TAB = NPTP * C * NDP;
   // B operand of the interpolation: lane group g supplies DoFs bdof(g, i), i < NB
   static constexpr int NB = KS;
   __device__ static constexpr int bdof(int g, int i) { return 4 * i + g; }
   // LDS bytes of the engine's tables (a multiple of 16)
   static constexpr int LDS_BYTES = (TAB * (int)sizeof(T) + 15) / 16 * 16;
 
-  // Tables from the global [NPT][4][NDOF + 1] layout into LDS.
+  // Tables from the global [NPT][4][NDOF + 1] layout into LDS (rows of
+  // points NPT..NPTP - 1 zero).
   __device__ static inline void setup(unsigned char* lds, const T* __restrict__ gtab, int tid, int nt) {
     T* s_tab = reinterpret_cast<T*>(lds);
     for (int i = tid; i < TAB; i += nt) {
       const int col = i % NDP, c = (i / NDP) % C, p = i / (NDP * C);
-      s_tab[i] = gtab[(p * 4 + c) * NDP + col];
+      s_tab[i] = p < NPT ? gtab[(p * 4 + c) * NDP + col] : T(0);
     }
   }
 
@@ -150,13 +155,12 @@ struct Tile {
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
       const int s = 4 * t + ri;
-      const bool ok = s < NS;
       const int base = ((gi + 4 * (s / C)) * C + s % C) * NDP;
       acc[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const int col = 4 * ks + g;
-        const T a = (ok && (NDOF % 4 == 0 || col < NDOF)) ? s_tab[base + col] : T(0);
+        const T a = (NDOF % 4 == 0 || col < NDOF) ? s_tab[base + col] : T(0);
         acc[t] = M::mma(a, ub[ks], acc[t]);
       }
     }
@@ -792,10 +796,10 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
     const T* tab = static_cast<const T*>(d.tab);
     for (int i = threadIdx.x; i < TC::TAB; i += kThreads) {
       const int col = i % TC::NDP, c = (i / TC::NDP) % C, p = i / (TC::NDP * C);
-      s_tab[i] = tab[(p * 4 + c) * TC::NDP + col];
+      s_tab[i] = p < TC::NPT ? tab[(p * 4 + c) * TC::NDP + col] : T(0);
     }
     const T* ftab = static_cast<const T*>(d.ftab);
-    for (int i = threadIdx.x; i < TF::TAB; i += kThreads) s_ftab[i] = ftab[i];
+    for (int i = threadIdx.x; i < TF::TAB; i += kThreads) s_ftab[i] = i < TF::NPT * 4 * TF::NDP ? ftab[i] : T(0);
     for (int i = threadIdx.x; i < TC::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
     for (int i = threadIdx.x; i < TF::NPT; i += kThreads) s_fw[i] = static_cast<const T*>(d.fw)[i];
     for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
