@@ -198,8 +198,11 @@ def bench_c2(args):
     ms = _time_call(lambda: op.apply(u, klc, klf, out=out), args.steps, args.warmup, op)
     kms, nl = op.profile_read()
     kms /= nl
+    # backward: du = A g (one apply) plus the cell and face coefficient gradients
+    g = torch.rand(op.n_dofs, dtype=torch.float64, device="cuda") * 2 - 1
+    ms_b = _time_call(lambda: op.backward(u, g, klc, kappa_face=klf, need_dkappa_face=True), args.steps, args.warmup)
     print(json.dumps({"metric": "DoFs/s per SIPG operator apply, P3, FP64", "value": round(op.n_dofs / (ms * 1e-3), 1),
-                      "unit": "DoFs/s", "ms_per_step": round(ms, 5), "dtype": "f64",
+                      "unit": "DoFs/s", "ms_per_step": round(ms, 5), "ms_backward": round(ms_b, 5), "dtype": "f64",
                       "config": {"workload": f"DG SIPG P3, {n}^3x6 Kuhn tets, lognormal(0,0.5) cell+face kappa, "
                                              f"Dirichlet mirror, 24/12-point rules", "n_dofs": op.n_dofs},
                       "roofline": roofline(op, "f64", kms)}), flush=True)

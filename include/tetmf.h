@@ -159,11 +159,18 @@ int tetmf_cell_data_layout(const tetmf_op* op, const void* src, void* dst, int t
 int tetmf_apply(tetmf_op* op, const void* u, const void* kappa_cell, const void* kappa_face, void* v,
                 void* stream);
 
-/* Backward of v = A(kappa) u for an upstream gradient g = dL/dv (CG):
- *  du = A^T g (= A g, the forms are symmetric) and
- *  dkappa_cell[q][e] = w_q |det J_e| (grad u . grad g)(x_q),
- * the derivative of g^T A(kappa) u.  du or dkappa_cell may be NULL.  Layouts
- * as for tetmf_apply.  UNSUPPORTED for DG. */
+/* Backward of v = A(kappa) u for an upstream gradient g = dL/dv: the
+ * derivatives of the bilinear forms of eq. (5) / eq. (7) (the paper gives no
+ * backward; these follow from differentiating the forms):
+ *  du = A^T g (= A g, both forms are symmetric) and the derivatives of
+ *  g^T A(kappa) u with respect to the coefficients:
+ *  dkappa_cell[q][e] = w_q |det J_e| (grad u . grad g)(x_q)            (CG, DG)
+ *  dkappa_face[q][F] (DG only) = omega_q (tau [[u]][[g]] - {{d_n u}}[[g]]
+ *        - [[u]]{{d_n g}}) on an interior face, omega_q (2 tau u g - g d_n u
+ *        - u d_n g) on a Dirichlet boundary face, 0 on a Neumann one.
+ * du, dkappa_cell or dkappa_face may be NULL; kappa_face and dkappa_face must
+ * be NULL for CG (INVALID_ARGUMENT).  Outputs must not alias each other or an
+ * input (ALIAS).  Layouts as for tetmf_apply.  UNSUPPORTED for BF16IN. */
 int tetmf_apply_backward(tetmf_op* op, const void* u, const void* g, const void* kappa_cell,
                          const void* kappa_face, void* du, void* dkappa_cell, void* dkappa_face,
                          void* stream);

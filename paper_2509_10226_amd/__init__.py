@@ -298,15 +298,22 @@ class Operator:
                                  _ptr(out, self.dtype, self.n_dofs, "v"), _stream()))
         return out
 
-    def backward(self, u, g, kappa_cell=None, need_du=True, need_dkappa=True):
+    def backward(self, u, g, kappa_cell=None, need_du=True, need_dkappa=True, kappa_face=None,
+                 need_dkappa_face=False):
+        """du = A g and dkappa_cell = d(g^T A u)/dkappa_cell (see
+        tetmf_apply_backward).  Returns (du, dkappa_cell), or, for a DG
+        operator with need_dkappa_face, (du, dkappa_cell, dkappa_face)."""
         torch = _torch()
-        du = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device()) if need_du else None
-        dk = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=self._device()) if need_dkappa else None
+        dev = self._device()
+        du = torch.empty(self.n_dofs, dtype=self.dtype, device=dev) if need_du else None
+        dk = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=dev) if need_dkappa else None
+        dkf = torch.empty((self.n_qf, self.n_face), dtype=self.dtype, device=dev) if need_dkappa_face else None
         _check(lib().tetmf_apply_backward(self._h, _ptr(u, self.dtype, self.n_dofs, "u"),
                                           _ptr(g, self.dtype, self.n_dofs, "g"),
                                           _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
-                                          None, _ptr(du), _ptr(dk), None, _stream()))
-        return du, dk
+                                          _ptr(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
+                                          _ptr(du), _ptr(dk), _ptr(dkf), _stream()))
+        return (du, dk, dkf) if need_dkappa_face else (du, dk)
 
     def diagonal(self, kappa_cell=None):
         torch = _torch()
@@ -383,21 +390,26 @@ def _autograd():
     torch = _torch()
 
     class ApplyFunction(torch.autograd.Function):
-        """v = A(kappa) u with a hand-written backward kernel:
-        dL/du = A^T dL/dv and dL/dkappa_q = w_q |det J| grad u . grad (dL/dv)."""
+        """v = A(kappa) u with hand-written backward kernels:
+        dL/du = A^T dL/dv, dL/dkappa_cell = w_q |det J| grad u . grad (dL/dv)
+        and, for DG, dL/dkappa_face from the face terms (tetmf_apply_backward)."""
 
         @staticmethod
-        def forward(ctx, u, kappa, op):
+        def forward(ctx, u, kappa, kappa_face, op):
             ctx.op = op
-            ctx.save_for_backward(u, kappa)
-            return op.apply(u.contiguous(), kappa.contiguous())
+            ctx.has_face = kappa_face is not None
+            ctx.save_for_backward(u, kappa, kappa_face)
+            return op.apply(u.contiguous(), kappa.contiguous(),
+                            kappa_face.contiguous() if kappa_face is not None else None)
 
         @staticmethod
         def backward(ctx, gv):
-            u, kappa = ctx.saved_tensors
-            du, dk = ctx.op.backward(u, gv.contiguous(), kappa, need_du=ctx.needs_input_grad[0],
-                                     need_dkappa=ctx.needs_input_grad[1])
-            return du, dk, None
+            u, kappa, kappa_face = ctx.saved_tensors
+            need_face = ctx.has_face and ctx.needs_input_grad[2]
+            out = ctx.op.backward(u, gv.contiguous(), kappa, need_du=ctx.needs_input_grad[0],
+                                  need_dkappa=ctx.needs_input_grad[1], kappa_face=kappa_face,
+                                  need_dkappa_face=need_face)
+            return out[0], out[1], out[2] if need_face else None, None
 
     return ApplyFunction
 
@@ -405,9 +417,10 @@ def _autograd():
 _APPLY_FN = None
 
 
-def apply_autograd(op, u, kappa):
-    """Differentiable v = A(kappa) u (kappa in library layout [n_q, n_cell])."""
+def apply_autograd(op, u, kappa, kappa_face=None):
+    """Differentiable v = A(kappa) u (kappa in library layout [n_q, n_cell];
+    kappa_face, DG only, [n_qf, n_face])."""
     global _APPLY_FN
     if _APPLY_FN is None:
         _APPLY_FN = _autograd()
-    return _APPLY_FN.apply(u, kappa, op)
+    return _APPLY_FN.apply(u, kappa, kappa_face, op)

@@ -951,6 +951,152 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
   }
 }
 
+// Coefficient gradients of the SIPG operator, d(g^T A(kappa) u) / dkappa:
+//   cell point q of cell e:   w_q (grad u . grad g)(x_q) |det J|
+//   face point q of face F:   omega_q (-{{d_n g}} [[u]] - [[g]] {{d_n u}} + tau [[u]] [[g]])   (interior)
+//                             omega_q (-g d_n u - u d_n g + 2 tau u g)                        (Dirichlet boundary)
+//                             0                                                               (Neumann boundary)
+// The bracket of an interior face is the same from either side; the side
+// with the smaller library cell id writes it, so every face point is written
+// once.  Traces are evaluated as in dg_kernel (common relabelled frame).
+// Two interpolated fields are live at once in the cell term, so the register
+// cap is relaxed to two waves per SIMD (no spills at P3 in FP64).
+template <typename T, int NDOF, int NQ, int NQF>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
+dg_grad_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ gv, T* __restrict__ dkc,
+               T* __restrict__ dkf) {
+  using TC = Tile<T, NDOF, NQ, 3>;
+  using TF = Tile<T, NDOF, NQF, 4>;
+  using M = Mfma<T>;
+  typedef typename M::acc_t acc_t;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s_tab = reinterpret_cast<T*>(smem);   // [NPTP][3][NDP]
+  T* s_ftab = s_tab + TC::TAB;              // [NPTF][4][NDP]
+  T* s_qw = s_ftab + TF::TAB;
+  T* s_fw = s_qw + TC::NPT;
+  int* s_perm = reinterpret_cast<int*>(s_fw + TF::NPT);
+  {
+    const T* tab = static_cast<const T*>(d.tab);
+    for (int i = threadIdx.x; i < TC::TAB; i += kThreads) {
+      const int col = i % TC::NDP, c = (i / TC::NDP) % 3, p = i / (TC::NDP * 3);
+      s_tab[i] = p < TC::NPT ? tab[(p * 4 + c) * TC::NDP + col] : T(0);
+    }
+    const T* ftab = static_cast<const T*>(d.ftab);
+    for (int i = threadIdx.x; i < TF::TAB; i += kThreads) s_ftab[i] = i < TF::NPT * 4 * TF::NDP ? ftab[i] : T(0);
+    for (int i = threadIdx.x; i < TC::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
+    for (int i = threadIdx.x; i < TF::NPT; i += kThreads) s_fw[i] = static_cast<const T*>(d.fw)[i];
+    for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6;
+  const int ncp = d.ncp, nc = d.n_cell, nf = d.n_face;
+  const T* geo = static_cast<const T*>(d.geo);
+  const T* fgeo = static_cast<const T*>(d.fgeo);
+  const int ntiles = ncp / kTile;
+  const int nx = 8, x = blockIdx.x % nx;
+  const int per = (gridDim.x / nx) * kWaves;
+  const int first = (int)((long long)ntiles * x / nx) + (blockIdx.x / nx) * kWaves + wave;
+  const int last = (int)((long long)ntiles * (x + 1) / nx);
+  for (int tile = first; tile < last; tile += per) {
+    const int tid = phase_tid();
+    const int lane = tid & 63;
+    const int g = lane >> 4, c16 = lane & 15;
+    const int cell = tile * kTile + c16;
+    const bool valid = cell < nc;
+    const int cc = valid ? cell : nc - 1;
+    if (dkc) {
+      T ub[TC::KS], gb[TC::KS];
+#pragma unroll
+      for (int s = 0; s < TC::KS; ++s) {
+        const int j = 4 * s + g;
+        ub[s] = (valid && j < NDOF) ? u[(long)cell * NDOF + j] : T(0);
+        gb[s] = (valid && j < NDOF) ? gv[(long)cell * NDOF + j] : T(0);
+      }
+      const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
+      const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
+      acc_t au[TC::MT], ag[TC::MT];
+      TC::interpolate(s_tab, ub, g, c16, au);
+      TC::interpolate(s_tab, gb, g, c16, ag);
+#pragma unroll
+      for (int k = 0; k < TC::KP; ++k) {
+        const int q = g + 4 * k;
+        const int i0 = 3 * k;
+        const T ux = au[i0 / 4][i0 % 4], uy = au[(i0 + 1) / 4][(i0 + 1) % 4], uz = au[(i0 + 2) / 4][(i0 + 2) % 4];
+        const T x_ = ag[i0 / 4][i0 % 4], y_ = ag[(i0 + 1) / 4][(i0 + 1) % 4], z_ = ag[(i0 + 2) / 4][(i0 + 2) % 4];
+        const T val = s_qw[q] * (ux * (G0 * x_ + G1 * y_ + G2 * z_) + uy * (G1 * x_ + G3 * y_ + G4 * z_) +
+                                 uz * (G2 * x_ + G4 * y_ + G5 * z_));
+        if (valid && q < NQ) dkc[(long)q * nc + cell] = val;
+      }
+    }
+    if (!dkf) continue;
+#pragma unroll 1
+    for (int f = 0; f < 4; ++f) {
+      const long fi = (long)f * ncp + cell;
+      const int nbc = valid ? d.nb[fi] : -1;
+      const int code = valid ? d.code[fi] : 0;
+      const int fidv = valid ? d.fid[fi] : 0;
+      const int ro = code & 255, rn = (code >> 8) & 255;
+      const bool boundary = nbc < 0;
+      // interior faces are written by the side with the smaller library cell id
+      const bool writer = valid && (boundary || cell < nbc);
+      T bo[3], bn[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        bo[q] = fgeo[((long)q * 4 + f) * ncp + cell];
+        bn[q] = fgeo[((long)(3 + q) * 4 + f) * ncp + cell];
+      }
+      const T om = fgeo[((long)6 * 4 + f) * ncp + cell];
+      const T tau = fgeo[((long)7 * 4 + f) * ncp + cell];
+      const int nbs = boundary ? cc : nbc;
+      // jump and average (own outward normal) of u, then of g, at the lane's points
+      T ju[TF::KP], au_[TF::KP], jg[TF::KP], ag_[TF::KP];
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        const T* w = pass == 0 ? u : gv;
+        T vm[TF::KS], vp[TF::KS];
+#pragma unroll
+        for (int s = 0; s < TF::KS; ++s) {
+          const int j = 4 * s + g;
+          const int jc = j < NDOF ? j : NDOF - 1;
+          const T a = w[(long)cc * NDOF + s_perm[ro * NDOF + jc]];
+          const T bq = w[(long)nbs * NDOF + s_perm[rn * NDOF + jc]];
+          vm[s] = (valid && j < NDOF) ? a : T(0);
+          vp[s] = (!boundary && j < NDOF) ? bq : T(0);
+        }
+        acc_t am[TF::MT], ap[TF::MT];
+        TF::interpolate(s_ftab, vm, g, c16, am);
+        TF::interpolate(s_ftab, vp, g, c16, ap);
+#pragma unroll
+        for (int k = 0; k < TF::KP; ++k) {
+          const T dnm = bo[0] * am[k][0] + bo[1] * am[k][1] + bo[2] * am[k][2];
+          const T dnp = bn[0] * ap[k][0] + bn[1] * ap[k][1] + bn[2] * ap[k][2];
+          // boundary: the one-sided value and normal derivative
+          const T jmp = boundary ? am[k][3] : am[k][3] - ap[k][3];
+          const T avg = boundary ? dnm : T(0.5) * (dnm + dnp);
+          if (pass == 0) {
+            ju[k] = jmp;
+            au_[k] = avg;
+          } else {
+            jg[k] = jmp;
+            ag_[k] = avg;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < TF::KP; ++k) {
+        const int q = g + 4 * k;
+        const T omq = s_fw[q] * om;
+        T val;
+        if (boundary)
+          val = d.dirichlet ? omq * (-jg[k] * au_[k] - ju[k] * ag_[k] + T(2) * tau * ju[k] * jg[k]) : T(0);
+        else
+          val = omq * (-ag_[k] * ju[k] - jg[k] * au_[k] + tau * ju[k] * jg[k]);
+        if (writer && q < NQF) dkf[(long)q * nf + fidv] = val;
+      }
+    }
+  }
+}
+
 template <typename T, int NDOF, int NQ, int NQF, int C>
 hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void* kf, void* v, hipStream_t s,
                        hipEvent_t* ev) {
@@ -983,6 +1129,39 @@ hipError_t launch_dg_shape(const DGDev& d, int ndof, int nq, int nqf, const void
   TETMF_DG_CASE(10, 14, 6)
   TETMF_DG_CASE(20, 24, 12)
 #undef TETMF_DG_CASE
+  *supported = false;
+  return hipSuccess;
+}
+
+template <typename T, int NDOF, int NQ, int NQF>
+hipError_t launch_dg_grad_t(const DGDev& d, const void* u, const void* g, void* dkc, void* dkf, hipStream_t s) {
+  using TC = Tile<T, NDOF, NQ, 3>;
+  using TF = Tile<T, NDOF, NQF, 4>;
+  const size_t lds = (size_t)(TC::TAB + TF::TAB + TC::NPT + TF::NPT) * sizeof(T) + 24 * NDOF * sizeof(int);
+  const int ntiles = d.ncp / kTile;
+  auto kern = dg_grad_kernel<T, NDOF, NQ, NQF>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int grid = persistent_grid((const void*)kern, lds, (ntiles + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)g, (T*)dkc, (T*)dkf);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dg_grad_shape(const DGDev& d, int ndof, int nq, int nqf, const void* u, const void* g, void* dkc,
+                                void* dkf, hipStream_t s, bool* supported) {
+  *supported = true;
+  if (ndof == 4 && nq == 4 && nqf == 3) return launch_dg_grad_t<T, 4, 4, 3>(d, u, g, dkc, dkf, s);
+  if (ndof == 10 && nq == 14 && nqf == 6) return launch_dg_grad_t<T, 10, 14, 6>(d, u, g, dkc, dkf, s);
+  if (ndof == 20 && nq == 24 && nqf == 12) return launch_dg_grad_t<T, 20, 24, 12>(d, u, g, dkc, dkf, s);
+  *supported = false;
+  return hipSuccess;
+}
+
+hipError_t launch_dg_grad(const DGDev& d, int prec, int ndof, int nq, int nqf, const void* u, const void* g,
+                          void* dkc, void* dkf, hipStream_t s, bool* supported) {
+  if (prec == PREC_F64) return launch_dg_grad_shape<double>(d, ndof, nq, nqf, u, g, dkc, dkf, s, supported);
+  if (prec == PREC_F32) return launch_dg_grad_shape<float>(d, ndof, nq, nqf, u, g, dkc, dkf, s, supported);
   *supported = false;
   return hipSuccess;
 }

@@ -1195,12 +1195,35 @@ extern "C" int tetmf_apply_backward(tetmf_op* op, const void* u, const void* g, 
                                     void* stream) {
   return guarded([&]() -> int {
     if (!op || !u || !g) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_apply_backward: NULL argument");
-    if (op->kind != TETMF_CG || kappa_face || dkappa_face)
-      return fail(TETMF_ERR_UNSUPPORTED, "tetmf_apply_backward: only continuous Galerkin operators");
+    if (op->kind == TETMF_CG && (kappa_face || dkappa_face))
+      return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_apply_backward: face coefficients given for a CG operator");
     if (du && (du == u || du == g)) return fail(TETMF_ERR_ALIAS, "tetmf_apply_backward: du aliases an input");
+    if ((dkappa_cell && (dkappa_cell == u || dkappa_cell == g || dkappa_cell == du)) ||
+        (dkappa_face && (dkappa_face == u || dkappa_face == g || dkappa_face == du || dkappa_face == dkappa_cell)))
+      return fail(TETMF_ERR_ALIAS, "tetmf_apply_backward: an output aliases another argument");
     if (op->prec == TETMF_BF16IN) return fail(TETMF_ERR_UNSUPPORTED, "tetmf_apply_backward: BF16 operands");
-    if (!du && !dkappa_cell) return TETMF_OK;
-    return run_cg(op, MODE_BACKWARD, u, g, kappa_cell, du, dkappa_cell, stream);
+    if (op->kind == TETMF_CG) {
+      if (!du && !dkappa_cell) return TETMF_OK;
+      return run_cg(op, MODE_BACKWARD, u, g, kappa_cell, du, dkappa_cell, stream);
+    }
+    // SIPG: A is symmetric, so du = A g is one forward apply; the coefficient
+    // gradients come from one pass over cells and faces.
+    DeviceScope ds(op->device);
+    hipStream_t s = (hipStream_t)stream;
+    bool supported = true;
+    if (du) {
+      hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, g, kappa_cell, kappa_face, du, s,
+                               &supported, nullptr);
+      if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
+      check_hip(e, "kernel launch");
+    }
+    if (dkappa_cell || dkappa_face) {
+      hipError_t e = launch_dg_grad(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, u, g, dkappa_cell,
+                                    dkappa_face, s, &supported);
+      if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
+      check_hip(e, "kernel launch");
+    }
+    return TETMF_OK;
   });
 }
 

@@ -28,7 +28,7 @@ def setup_dg(n, p, bc="dirichlet", kappa=True, precision="f64", shuffle=False, s
     dev = torch.device("cuda", 0)
     klc = None if kc is None else op.cell_data_to_library(torch.from_numpy(kc).to(dev))
     klf = None if kf is None else torch.from_numpy(kf.T.copy()).to(dev, op.dtype)
-    return dict(A=A, op=op, idx=idx, klc=klc, klf=klf, dev=dev)
+    return dict(A=A, op=op, idx=idx, klc=klc, klf=klf, dev=dev, mesh=(xyz, tets), rules=(qp, qw, fp, fw))
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
@@ -57,3 +57,73 @@ def test_dg_mass_and_determinism():
     v2 = c["op"].apply(ut, c["klc"], c["klf"])
     assert torch.equal(v1, v2)
     assert rel_err(v1.cpu().numpy(), (c["A"] @ u)[c["idx"]]) <= 1e-12
+
+
+@pytest.mark.parametrize("p,bc,precision", [(1, "dirichlet", "f64"), (2, "neumann", "f64"), (3, "dirichlet", "f64"),
+                                            (3, "neumann", "f32"), (2, "dirichlet", "f32")])
+def test_dg_backward_vs_oracle(p, bc, precision):
+    """du = A g and the cell and face coefficient gradients of g^T A u against
+    the oracle (which is pinned to indicator-coefficient assembly)."""
+    c = setup_dg(4, p, bc=bc, precision=precision, shuffle=(precision == "f32"), mass=0.5)
+    op, idx, dev = c["op"], c["idx"], c["dev"]
+    n = c["A"].shape[0]
+    u = synth.uniform(0, synth.STREAM_U, n)
+    g = synth.uniform(0, synth.STREAM_F, n)
+    ut = torch.from_numpy(u[idx]).to(dev, op.dtype)
+    gt = torch.from_numpy(g[idx]).to(dev, op.dtype)
+    du, dk, dkf = op.backward(ut, gt, c["klc"], kappa_face=c["klf"], need_dkappa_face=True)
+    tol = 1e-12 if precision == "f64" else 1e-5
+    assert rel_err(du.double().cpu().numpy(), (c["A"].T @ g)[idx]) <= tol
+    xyz, tets = c["mesh"]
+    qp, qw, fp, fw = c["rules"]
+    dkc_o, dkf_o = oracle.dg_kappa_grad(xyz, tets, p, qp, qw, fp, fw, u, g, bc=bc)
+    dkc = op.cell_data_to_user(dk).cpu().numpy()
+    assert rel_err(dkc, dkc_o) <= tol
+    dkf_g = dkf.double().cpu().numpy().T
+    assert rel_err(dkf_g, dkf_o) <= tol
+    if bc == "neumann":
+        bnd = np.flatnonzero(np.all(dkf_o == 0.0, axis=1))
+        assert bnd.size > 0 and np.all(dkf_g[bnd] == 0.0)
+    # each output alone matches the joint call
+    _, dk2 = op.backward(ut, gt, c["klc"], need_du=False)
+    assert torch.equal(dk2, dk)
+    _, _, dkf2 = op.backward(ut, gt, need_du=False, need_dkappa=False, need_dkappa_face=True)
+    assert torch.equal(dkf2, dkf)
+
+
+def test_dg_backward_directional_derivative():
+    """g^T A(kappa + h dk) u - g^T A(kappa - h dk) u over 2h equals
+    <dkappa, dk> (the forms are linear in kappa, so the difference quotient
+    is exact up to rounding)."""
+    c = setup_dg(3, 2, bc="dirichlet")
+    op, idx, dev = c["op"], c["idx"], c["dev"]
+    n = c["A"].shape[0]
+    ut = torch.from_numpy(synth.uniform(1, synth.STREAM_U, n)[idx]).to(dev)
+    gt = torch.from_numpy(synth.uniform(1, synth.STREAM_F, n)[idx]).to(dev)
+    _, dk, dkf = op.backward(ut, gt, c["klc"], kappa_face=c["klf"], need_du=False, need_dkappa_face=True)
+    pc = torch.from_numpy(synth.uniform(2, synth.STREAM_U, dk.numel())).to(dev).reshape(dk.shape)
+    pf = torch.from_numpy(synth.uniform(3, synth.STREAM_U, dkf.numel())).to(dev).reshape(dkf.shape)
+    h = 1e-3
+
+    def form(s):
+        return torch.dot(gt, op.apply(ut, c["klc"] + s * pc, c["klf"] + s * pf)).item()
+    fd = (form(h) - form(-h)) / (2 * h)
+    an = (torch.sum(dk * pc) + torch.sum(dkf * pf)).item()
+    assert abs(fd - an) <= 1e-9 * max(1.0, abs(an))
+
+
+def test_dg_autograd_matches_backward():
+    """torch.autograd through apply_autograd returns the kernel gradients."""
+    import paper_2509_10226_amd as tm
+    c = setup_dg(3, 3, bc="dirichlet")
+    op, idx, dev = c["op"], c["idx"], c["dev"]
+    n = c["A"].shape[0]
+    ut = torch.from_numpy(synth.uniform(4, synth.STREAM_U, n)[idx]).to(dev).requires_grad_()
+    gt = torch.from_numpy(synth.uniform(4, synth.STREAM_F, n)[idx]).to(dev)
+    kc = c["klc"].clone().requires_grad_()
+    kf = c["klf"].clone().requires_grad_()
+    v = tm.apply_autograd(op, ut, kc, kf)
+    (v * gt).sum().backward()
+    du, dk, dkf = op.backward(ut.detach(), gt, c["klc"], kappa_face=c["klf"], need_dkappa_face=True)
+    assert torch.equal(ut.grad, du) and torch.equal(kc.grad, dk) and torch.equal(kf.grad, dkf)
+    assert rel_err(du.cpu().numpy(), (c["A"] @ synth.uniform(4, synth.STREAM_F, n))[idx]) <= 1e-12
