@@ -9,7 +9,8 @@ the velocity step of the dual splitting in Sec. 4.2):
                                     + sigma phi_i phi_j )  at x_q,
 
 with grad phi = J^{-T} grad_ref phi (Sec. 2.2).  A = sum_e G_e^T A_e G_e
-(eq. (5)).  Homogeneous Dirichlet: constrained rows and columns are replaced
+(eq. (5)).  Curved cells (Sec. 3.2) use the Jacobian J_q of the
+reference-to-physical map at each point instead of the affine J.  Homogeneous Dirichlet: constrained rows and columns are replaced
 by the identity, the reading that a masked gather skips constrained DoFs
 (Sec. 2.4, instruction scheduling) and the operator returns them unchanged.
 
@@ -37,18 +38,30 @@ from .basis import eval_basis, nodes
 from .mesh import Geometry, cg_dofs, find_faces
 
 
-def _cell_matrices(geo, cells, p, qpts, qw, kappa, sigma):
+def _point_geometry(geo, cells, nq, jac):
+    """J^{-1} and |det J| at every rule point: [e, q, 3, 3] and [e, q].
+
+    Straight-sided cells repeat the affine values; curved cells (Sec. 3.2)
+    take the Jacobian of the reference-to-physical map at each point, given
+    as jac [n_cell, n_q, 3, 3] with jac[e, q, a, b] = d x_a / d xi_b."""
+    if jac is None:
+        Jinv = np.repeat(geo.Jinv[cells][:, None], nq, axis=1)
+        adet = np.repeat(np.abs(geo.detJ[cells])[:, None], nq, axis=1)
+        return Jinv, adet
+    Jq = np.asarray(jac, dtype=np.float64)[cells]
+    return np.linalg.inv(Jq), np.abs(np.linalg.det(Jq))
+
+
+def _cell_matrices(geo, cells, p, qpts, qw, kappa, sigma, jac=None):
     """Element matrices [len(cells), n_dof, n_dof] (stiffness with kappa + sigma*mass)."""
     phi, gref = eval_basis(p, qpts)  # [nq, nd], [nq, 3, nd]
-    Jinv = geo.Jinv[cells]
-    adet = np.abs(geo.detJ[cells])
-    B = np.einsum("eji,qjk->eqik", Jinv, gref)  # J^{-T} grad_ref: [e, q, 3, nd]
+    Jinv, adet = _point_geometry(geo, cells, qw.size, jac)
+    B = np.einsum("eqji,qjk->eqik", Jinv, gref)  # J^{-T} grad_ref: [e, q, 3, nd]
     kap = np.ones((cells.size, qw.size)) if kappa is None else kappa[cells]
-    s = qw[None, :] * adet[:, None] * kap
+    s = qw[None, :] * adet * kap
     A = np.einsum("eq,eqik,eqil->ekl", s, B, B)
     if sigma:
-        M = np.einsum("q,qk,ql->kl", qw, phi, phi)
-        A = A + sigma * adet[:, None, None] * M[None]
+        A = A + sigma * np.einsum("eq,qk,ql->ekl", qw[None, :] * adet, phi, phi)
     return A
 
 
@@ -57,8 +70,10 @@ def _chunks(n, size=20000):
         yield np.arange(s, min(n, s + size))
 
 
-def assemble_cg(xyz, tets, p, qpts, qw, kappa=None, sigma=0.0, dirichlet=False, dofs=None):
-    """Global CG matrix (CSR, FP64) and the DoF description from ``cg_dofs``."""
+def assemble_cg(xyz, tets, p, qpts, qw, kappa=None, sigma=0.0, dirichlet=False, dofs=None, jac=None):
+    """Global CG matrix (CSR, FP64) and the DoF description from ``cg_dofs``.
+    jac: per-point Jacobians of curved cells (see ``_point_geometry``); the
+    DoF identities still come from the straight-sided vertex mesh."""
     geo = Geometry(xyz, tets)
     if np.any(geo.detJ <= 0):
         raise ValueError("oracle expects positively oriented cells")
@@ -67,7 +82,7 @@ def assemble_cg(xyz, tets, p, qpts, qw, kappa=None, sigma=0.0, dirichlet=False, 
     n = d["xyz"].shape[0]
     rows, cols, vals = [], [], []
     for c in _chunks(geo.n_cell):
-        Ae = _cell_matrices(geo, c, p, qpts, qw, kappa, sigma)
+        Ae = _cell_matrices(geo, c, p, qpts, qw, kappa, sigma, jac)
         nd = dm.shape[1]
         rows.append(np.repeat(dm[c], nd, axis=1).ravel())
         cols.append(np.tile(dm[c], (1, nd)).ravel())
@@ -87,7 +102,7 @@ def _apply_dirichlet(A, constrained):
     return A
 
 
-def cg_kappa_grad(xyz, tets, p, qpts, qw, u, g, dofs=None):
+def cg_kappa_grad(xyz, tets, p, qpts, qw, u, g, dofs=None, jac=None):
     """d(g^T A(kappa) u) / d kappa_{e,q} = w_q |det J| (grad u . grad g)(x_q)."""
     geo = Geometry(xyz, tets)
     d = cg_dofs(xyz, tets, p) if dofs is None else dofs
@@ -95,21 +110,23 @@ def cg_kappa_grad(xyz, tets, p, qpts, qw, u, g, dofs=None):
     _, gref = eval_basis(p, qpts)
     out = np.empty((geo.n_cell, qw.size))
     for c in _chunks(geo.n_cell):
-        B = np.einsum("eji,qjk->eqik", geo.Jinv[c], gref)
+        Jinv, adet = _point_geometry(geo, c, qw.size, jac)
+        B = np.einsum("eqji,qjk->eqik", Jinv, gref)
         gu = np.einsum("eqik,ek->eqi", B, u[dm[c]])
         gg = np.einsum("eqik,ek->eqi", B, g[dm[c]])
-        out[c] = qw[None, :] * np.abs(geo.detJ[c])[:, None] * np.sum(gu * gg, axis=2)
+        out[c] = qw[None, :] * adet * np.sum(gu * gg, axis=2)
     return out
 
 
-def load_vector(xyz, tets, p, qpts, qw, f=None, dirichlet=False, dofs=None):
+def load_vector(xyz, tets, p, qpts, qw, f=None, dirichlet=False, dofs=None, jac=None):
     """b_i = sum_e sum_q w_q |det J| f_{e,q} phi_i(x_q); zero on constrained rows."""
     geo = Geometry(xyz, tets)
     d = cg_dofs(xyz, tets, p) if dofs is None else dofs
     dm = d["dofmap"]
     phi, _ = eval_basis(p, qpts)
     fv = np.ones((geo.n_cell, qw.size)) if f is None else f
-    loc = np.einsum("eq,qk->ek", qw[None, :] * np.abs(geo.detJ)[:, None] * fv, phi)
+    _, adet = _point_geometry(geo, np.arange(geo.n_cell), qw.size, jac)
+    loc = np.einsum("eq,qk->ek", qw[None, :] * adet * fv, phi)
     b = np.zeros(d["xyz"].shape[0])
     np.add.at(b, dm.ravel(), loc.ravel())
     if dirichlet:
@@ -279,7 +296,7 @@ def dg_kappa_grad(xyz, tets, p, qpts, qw, fpts, fw, u, g, eta=1.0, bc="dirichlet
 # ---------------------------------------------------------------------------
 # selected rows for large meshes
 
-def cg_rows(xyz, tets, p, qpts, qw, cell_of_row, local_of_row, kappa=None, sigma=0.0):
+def cg_rows(xyz, tets, p, qpts, qw, cell_of_row, local_of_row, kappa=None, sigma=0.0, jac=None):
     """Rows of the CG matrix for DoFs given as (cell, local node) pairs.
 
     Returns a list of dicts {column key: value}, where a key is the sorted
@@ -305,7 +322,7 @@ def cg_rows(xyz, tets, p, qpts, qw, cell_of_row, local_of_row, kappa=None, sigma
         support = [v for v, _ in rk]
         cand = order[starts[support[0]]:starts[support[0] + 1]] // 4
         cells = np.array(sorted(c for c in set(cand.tolist()) if all(v in tets[c] for v in support)))
-        Ae = _cell_matrices(geo, cells, p, qpts, qw, kappa, sigma)
+        Ae = _cell_matrices(geo, cells, p, qpts, qw, kappa, sigma, jac)
         row = {}
         for ci, c in enumerate(cells):
             jj = [j for j in range(al.shape[0]) if key(c, j) == rk]

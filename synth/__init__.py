@@ -20,6 +20,14 @@ seeded shuffle of cell and vertex order stands in for its "unordered" state):
   (n_vert, 3))`` is drawn for all vertices in id order and the rows of
   boundary vertices are zeroed, so the domain stays the unit cube.
 
+Curved cells (a stand-in for curvilinear meshes, Sec. 3.2): the straight
+mesh is pushed through the smooth global map
+    Phi(x, y, z) = (x + e y^2, y + e z^2, z + e x^2),
+so the reference-to-physical map of cell K is Phi(X0 + J_K xi) and its
+Jacobian at a reference point xi is grad Phi(X) J_K, X = X0 + J_K xi.
+``curved_jacobians`` tabulates these per cell and rule point (the input a
+curvilinear operator receives); ``curved_map`` applies Phi to points.
+
 Random streams: ``default_rng([seed, s])`` with s = 1 cell coefficients,
 2 input vector, 3 face coefficients, 4 right-hand side f, 5 finite-difference
 picks, 9 shuffle permutations.
@@ -150,3 +158,24 @@ def five_tet_cube_mesh(n):
                         ids[2], ids[3] = ids[3], ids[2]
                     out.append(ids)
     return xyz, np.array(out, dtype=np.int32)
+
+
+def curved_map(x, eps):
+    """Phi applied to points x [..., 3] (see the module docstring)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.stack([x[..., 0] + eps * x[..., 1] ** 2, x[..., 1] + eps * x[..., 2] ** 2,
+                     x[..., 2] + eps * x[..., 0] ** 2], axis=-1)
+
+
+def curved_jacobians(xyz, tets, qpts, eps):
+    """[n_cell, n_q, 3, 3] Jacobians d x / d xi of Phi(X0 + J_K xi) at the
+    rule points, row a = physical coordinate, column b = reference one."""
+    X = np.asarray(xyz, dtype=np.float64)[np.asarray(tets)]
+    JK = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
+    P = X[:, None, 0, :] + np.einsum("eab,qb->eqa", JK, np.asarray(qpts, dtype=np.float64))
+    x, y, z = P[..., 0], P[..., 1], P[..., 2]
+    one, zero = np.ones_like(x), np.zeros_like(x)
+    D = np.stack([np.stack([one, 2 * eps * y, zero], -1),
+                  np.stack([zero, one, 2 * eps * z], -1),
+                  np.stack([2 * eps * x, zero, one], -1)], -2)
+    return np.einsum("eqab,ebc->eqac", D, JK)
