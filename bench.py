@@ -86,16 +86,18 @@ def time_gpu(op, kl, u, steps, warmup):
     return (t1 - t0) * 1e3 / steps, ms_kernel / launches, out
 
 
-def roofline(op, prec, avg_ms):
-    """Roofline of the cell kernel.  FP64 and FP32 are compute-bound by the
-    algorithmic intensity (flops/byte above the ridge point); with BF16
-    operands the matrix-core peak is 16x higher and the HBM roof binds."""
+def roofline(op, prec, avg_ms, traffic_key=None):
+    """Roofline of the cell kernel, bound chosen by the algorithmic intensity
+    (flops per byte) against the ridge point peak flops / peak HBM bandwidth:
+    straight-sided FP64 and FP32 are compute-bound; BF16 operands (16x the
+    matrix-core peak) and curved cells (a geometry per point) are HBM-bound."""
     flops = op.info["flops_per_apply"]
     bytes_alg = op.info["bytes_per_apply"]
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    traffic = read_traffic(prec)
+    traffic = read_traffic(prec) if traffic_key is None else None
     gbs = bytes_alg / (avg_ms * 1e-3) / 1e9
-    if prec == "bf16in":
+    ridge = PEAK_TFLOPS[prec] * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if flops / bytes_alg < ridge:
         return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic, "algorithmic_flops": flops,
                 "algorithmic_bytes": bytes_alg, "mfma_achieved_TFLOPs": round(achieved, 3),
@@ -331,6 +333,38 @@ def bench_f1(args):
           flush=True)
 
 
+def bench_f3(args):
+    """Curved cells (a Jacobian per rule point, Sec. 3.2): the measured
+    workload's mesh pushed through a smooth global map, CG P3 with the
+    24-point rule, FP64 and FP32, next to the straight-sided operator."""
+    import torch
+
+    import paper_2509_10226_amd as tm
+    import synth
+    xyz, tets, qp, qw, kap = build_workload(args.n)
+    jac = synth.curved_jacobians(xyz, tets, qp, 0.25)
+    mesh = tm.Mesh(xyz, tets)
+    res = {}
+    for prec in ("f64", "f32"):
+        for curved in (True, False):
+            op = tm.Operator(mesh, 3, (qp, qw), precision=prec, q_jacobians=jac if curved else None)
+            kl = op.cell_data_to_library(torch.from_numpy(kap).cuda())
+            g = torch.Generator(device="cpu").manual_seed(2)
+            u = (torch.rand(op.n_dofs, generator=g, dtype=torch.float64) * 2 - 1).to("cuda", op.dtype)
+            ms_step, ms_kernel, _ = time_gpu(op, kl, u, args.steps, args.warmup)
+            res[f"{'curved' if curved else 'straight'}_{prec}"] = {
+                "DoFs_per_s": round(op.n_dofs / (ms_step * 1e-3), 1), "ms_per_step": round(ms_step, 5),
+                "kernel_ms": round(ms_kernel, 5), "device_bytes": op.info["device_bytes"],
+                "roofline": roofline(op, prec, ms_kernel, traffic_key="curved" if curved else None)}
+            del op
+    print(json.dumps({"metric": "DoFs/s per operator apply, CG P3 on curved cells (per-point Jacobians)",
+                      "value": res["curved_f64"]["DoFs_per_s"], "unit": "DoFs/s", "dtype": "f64",
+                      "config": {"workload": f"CG P3 Poisson, {args.n}^3x6 Kuhn tets mapped by "
+                                             "(x + 0.25 y^2, y + 0.25 z^2, z + 0.25 x^2), lognormal(0,1) kappa, "
+                                             "24-point rule"},
+                      "variants": res}), flush=True)
+
+
 def bench_f4(args):
     """Jacobi-preconditioned Chebyshev smoothing (degree 5, as in the
     multigrid of Sec. 4.1) on the solve workload, FP64 and FP32: time per
@@ -376,8 +410,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=64, help="cubes per axis (64 = the measured workload)")
     ap.add_argument("--precisions", default="f64,f32,bf16in")
-    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5", "order", "f1", "f4"],
-                    help="c3 (default): the measured workload; c2/c4/c5/order/f1/f4: secondary measurements, "
+    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5", "order", "f1", "f3", "f4"],
+                    help="c3 (default): the measured workload; c2/c4/c5/order/f1/f3/f4: secondary measurements, "
                          "each printed as its own JSON line")
     ap.add_argument("--order-variant", default="all",
                     choices=["all", "native_locality", "shuffled_locality", "shuffled_as_given"])
@@ -396,7 +430,7 @@ def main():
         return
     if args.config != "c3":
         {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "order": bench_order, "f1": bench_f1,
-         "f4": bench_f4}[args.config](args)
+         "f3": bench_f3, "f4": bench_f4}[args.config](args)
         return
     dev = torch.device("cuda", 0)
     xyz, tets, qp, qw, kap = build_workload(args.n)

@@ -89,6 +89,16 @@ typedef struct {
   double sigma;        /* mass coefficient of the Helmholtz-type form (0 = Poisson) */
   double eta;          /* SIPG penalty factor: tau_F = eta (p+1)^2 |F| / min|K| */
   int32_t device;      /* HIP device ordinal */
+  /* Curved cells (Sec. 3.2), CG only: NULL for straight-sided cells (the
+   * affine map of each tetrahedron's vertices), or the Jacobian of each
+   * cell's reference-to-physical map at each cell rule point, host
+   * [n_cell][n_q][3][3] in user cell order, J[a][b] = d x_a / d xi_b.  The
+   * operator then stores G_q = |det J_q| J_q^-1 J_q^-T (and |det J_q| with a
+   * mass term) per point and reads it in every apply: 6 n_q (7 n_q) values
+   * per cell instead of 6 (7).  The vertex mesh still defines the DoF
+   * connectivity and tetmf_op_numbering's coordinates.  DG: UNSUPPORTED.
+   * DEGENERATE_CELL when some |det J_q| <= 1e-12 |J_q|_F^3 or is not finite. */
+  const double* q_jacobians;
 } tetmf_op_desc;
 
 typedef struct {

@@ -39,6 +39,7 @@ class OpDesc(ctypes.Structure):
         ("n_q", ctypes.c_int32), ("q_points", ctypes.c_void_p), ("q_weights", ctypes.c_void_p),
         ("n_qf", ctypes.c_int32), ("qf_points", ctypes.c_void_p), ("qf_weights", ctypes.c_void_p),
         ("sigma", ctypes.c_double), ("eta", ctypes.c_double), ("device", ctypes.c_int32),
+        ("q_jacobians", ctypes.c_void_p),
     ]
 
 
@@ -173,7 +174,8 @@ class Mesh:
             self._h = None
 
 
-def _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, device):
+def _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, device, mesh=None,
+               q_jacobians=None):
     qp, qw = (np.ascontiguousarray(a, dtype=np.float64) for a in qrule)
     d = OpDesc()
     d.kind = _KIND[kind]
@@ -194,14 +196,20 @@ def _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, 
     d.sigma = float(sigma)
     d.eta = float(eta)
     d.device = int(device)
+    if q_jacobians is not None:
+        jac = np.ascontiguousarray(q_jacobians, dtype=np.float64)
+        if jac.shape != (mesh.tets.shape[0], qw.size, 3, 3):
+            raise ValueError(f"q_jacobians must have shape [{mesh.tets.shape[0]}, {qw.size}, 3, 3]")
+        d.q_jacobians = jac.ctypes.data
+        keep.append(jac)
     return d, keep
 
 
 def check_setup(mesh, degree, qrule, kind="cg", frule=None, precision="f64", bc="neumann", sigma=0.0, eta=1.0,
-                ordering="locality"):
+                ordering="locality", q_jacobians=None):
     """Host-only run of the operator set-up with its invariant checks (no GPU
     needed); returns (n_dofs, n_free) or raises TetmfError."""
-    d, keep = _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, 0)
+    d, keep = _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, 0, mesh, q_jacobians)
     nd, nf = ctypes.c_int64(), ctypes.c_int64()
     _check(lib().tetmf_op_check(mesh._h, ctypes.byref(d), ctypes.byref(nd), ctypes.byref(nf)))
     del keep
@@ -212,30 +220,15 @@ class Operator:
     """Matrix-free operator A(kappa) on a mesh (see include/tetmf.h)."""
 
     def __init__(self, mesh, degree, qrule, kind="cg", frule=None, precision="f64", bc="neumann",
-                 sigma=0.0, eta=1.0, ordering="locality", device=0):
+                 sigma=0.0, eta=1.0, ordering="locality", device=0, q_jacobians=None):
+        """q_jacobians: None (straight-sided cells) or [n_cell, n_q, 3, 3]
+        Jacobians of curved cells at the rule points (tetmf_op_desc)."""
         L = lib()
-        qp, qw = (np.ascontiguousarray(a, dtype=np.float64) for a in qrule)
-        d = OpDesc()
-        d.kind = _KIND[kind]
-        d.degree = int(degree)
-        d.bc = _BC[bc]
-        d.precision = _PREC[precision]
-        d.ordering = _ORDER[ordering]
-        d.n_q = qw.size
-        d.q_points = qp.ctypes.data
-        d.q_weights = qw.ctypes.data
-        self._keep = [qp, qw]
-        if frule is not None:
-            fp, fw = (np.ascontiguousarray(a, dtype=np.float64) for a in frule)
-            d.n_qf = fw.size
-            d.qf_points = fp.ctypes.data
-            d.qf_weights = fw.ctypes.data
-            self._keep += [fp, fw]
-        d.sigma = float(sigma)
-        d.eta = float(eta)
-        d.device = int(device)
+        d, keep = _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, device, mesh,
+                             q_jacobians)
         h = ctypes.c_void_p()
         _check(L.tetmf_op_create(mesh._h, ctypes.byref(d), ctypes.byref(h)))
+        del keep
         self._h = h
         self.kind, self.precision, self.degree = kind, precision, degree
         self.device = int(device)

@@ -28,8 +28,10 @@ struct CGDev {
   int n_cell, ncp, n_dofs, n_free, n_blocks, n_shared;
   int nq;                 // quadrature points (<= 4 * MT of the kernel)
   int nbd_max;            // largest number of DoFs of one block
+  int curved;             // geo holds one entry per rule point (see geo)
   double sigma;           // mass coefficient
-  const void* geo;        // [7][ncp]: G00 G01 G02 G11 G12 G22 (= |detJ| J^-1 J^-T), |detJ|
+  const void* geo;        // [7][ncp]: G00 G01 G02 G11 G12 G22 (= |detJ| J^-1 J^-T), |detJ|;
+                          // curved: [7][nq][ncp], the same per rule point
   const void* tab;        // basis table, layout chosen by the precision (see kernels.hip)
   const void* qw;         // [4*MT] quadrature weights, zero beyond nq
   const int* blk_priv_start;  // [n_blocks] first id of the block's private DoF range

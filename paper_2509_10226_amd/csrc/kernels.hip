@@ -402,7 +402,28 @@ __device__ inline void cg_reduce(const CGDev& d, const T* __restrict__ s_slot, i
   }
 }
 
-template <typename T, int NDOF, int NQ, int C, int MODE, bool BF>
+// Geometry of one rule point of the lane's cell for curved cells: row
+// (c, q) of the [7][NQ][ncp] table, q = g + 4k clamped to the rule, read
+// with a wave-uniform row base (c, 4k) and a 32-bit lane offset.
+// dep: a value computed just before; the offset passes through an empty asm
+// that depends on it, so the loads are issued there and not hoisted (the
+// matrix-core tiles need the registers).
+// G[7] receives the coefficient at the point (1 without one; cc: the cell
+// clamped to the mesh).
+template <typename T, int NQ, int C>
+__device__ inline void point_geo(const T* __restrict__ geo, int ncp, const T* __restrict__ kappa, int nc, int k,
+                                 int g, int cell, int cc, T dep, T (&G)[8]) {
+  const int q = min(g + 4 * k, NQ - 1);
+  uint32_t off = ((uint32_t)(q - 4 * k) * (uint32_t)ncp + (uint32_t)cell) * (uint32_t)sizeof(T);
+  uint32_t kof = ((uint32_t)(q - 4 * k) * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T);
+  asm volatile("" : "+v"(off), "+v"(kof) : "v"(dep));
+#pragma unroll
+  for (int c = 0; c < (C == 4 ? 7 : 6); ++c) G[c] = load_at(geo + ((long)c * NQ + 4 * k) * ncp, off);
+  if (C != 4) G[6] = T(0);
+  G[7] = kappa ? load_at(kappa + (long)(4 * k) * nc, kof) : T(1);
+}
+
+template <typename T, int NDOF, int NQ, int C, int MODE, bool BF, bool CURV>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* __restrict__ kappa,
           T* __restrict__ out, T* __restrict__ dk) {
@@ -431,6 +452,11 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
     const int oo = d.blk_other_off[b], po = d.blk_ptr_off[b];
     __syncthreads();  // previous block's slots, staged values and indices are consumed
     {
+      // curved cells: thread index re-derived per block, so that the staging
+      // addresses are not kept live across the compute phase (which needs
+      // the registers for the per-point geometry; the straight kernels are
+      // faster with them kept)
+      const unsigned st = CURV ? (unsigned)phase_tid() : threadIdx.x;
       // block-local indices: [NDOF][kBlockCells] uint16, copied as 32-bit words
       const uint32_t* src = reinterpret_cast<const uint32_t*>(d.lidx);
       uint32_t* dstw = reinterpret_cast<uint32_t*>(s_lidx);
@@ -438,7 +464,7 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
       uint32_t wv[(W + kThreads - 1) / kThreads];
 #pragma unroll
       for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
-        const int w = i * kThreads + threadIdx.x;
+        const int w = i * kThreads + st;
         const int j = (2 * w) / kBlockCells, cl = (2 * w) % kBlockCells;
         wv[i] = w < W ? src[((long)j * ncp + (long)b * kBlockCells + cl) / 2] : 0u;
       }
@@ -451,7 +477,7 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
         bool ok[kStageUnroll];
 #pragma unroll
         for (int i = 0; i < kStageUnroll; ++i) {
-          const int k = k0 + i * kThreads + threadIdx.x;
+          const int k = k0 + i * kThreads + st;
           const int oi = min(max(k - npriv, 0), max(nother - 1, 0));
           const int og = d.other_gid[oo + oi];
           gi[i] = (k < npriv) ? ps + k : og;
@@ -468,7 +494,7 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
         }
 #pragma unroll
         for (int i = 0; i < kStageUnroll; ++i) {
-          const int k = k0 + i * kThreads + threadIdx.x;
+          const int k = k0 + i * kThreads + st;
           if (k < nbd) {
             s_u[k] = uv[i];
             if (BWD) s_u[d.nbd_max + k] = gv[i];
@@ -477,7 +503,7 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
       }
 #pragma unroll
       for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
-        const int w = i * kThreads + threadIdx.x;
+        const int w = i * kThreads + st;
         if (w < W) dstw[w] = wv[i];
       }
     }
@@ -492,15 +518,20 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
       const int cell = b * kBlockCells + cl;
       const bool valid = cell < nc;
       // per-cell arrays: row base (uniform) + 32-bit lane offset
-      const uint32_t coff = (uint32_t)cell * (uint32_t)sizeof(T);
-      const T G0 = load_at(geo, coff), G1 = load_at(geo + ncp, coff), G2 = load_at(geo + 2 * (long)ncp, coff);
-      const T G3 = load_at(geo + 3 * (long)ncp, coff), G4 = load_at(geo + 4 * (long)ncp, coff);
-      const T G5 = load_at(geo + 5 * (long)ncp, coff);
-      const T adet = (C == 4) ? load_at(geo + 6 * (long)ncp, coff) : T(0);
+      // straight cells: G and |det J| of the cell (curved: per point below)
+      T Gc[7];
+      if constexpr (!CURV) {
+        const uint32_t coff = (uint32_t)cell * (uint32_t)sizeof(T);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Gc[c] = load_at(geo + c * (long)ncp, coff);
+        Gc[6] = (C == 4) ? load_at(geo + 6 * (long)ncp, coff) : T(0);
+      }
       // coefficient at this lane's points q = g + 4k (row q of [NQ][nc]),
       // from a clamped (always valid) address and masked afterwards
       T kq[KP];
-      if (kappa) {
+      if (CURV) {
+        // loaded with the per-point geometry
+      } else if (kappa) {
         const int cc = valid ? cell : nc - 1;
         const uint32_t kof = ((uint32_t)g * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T);
 #pragma unroll
@@ -550,13 +581,31 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
 #pragma unroll
         for (int t = 0; t < MT; ++t) accg[BWD ? t : 0] = tmp[t];
       }
-      // point operator D in registers: item s = C k + c at acc[s / 4][s % 4]
+      // point operator D in registers: item s = C k + c at acc[s / 4][s % 4].
+      // Curved cells: the geometry of point k + 1 is requested once point
+      // k - 1 is done (two points' geometry live at a time).
+      const int ccell = valid ? cell : nc - 1;
+      // per-tile copies of the bases, so that the row addresses derived from
+      // them are not hoisted out of the block loop (36 of them at P3)
+      const T* geot = geo;
+      const T* kapt = kappa;
+      if constexpr (CURV) asm volatile("" : "+s"(geot), "+s"(kapt));
 #pragma unroll
       for (int k = 0; k < KP; ++k) {
+        T Gk[8];
+        if constexpr (CURV) {
+          const int ip = C * (k > 0 ? k - 1 : 0);
+          point_geo<T, NQ, C>(geot, ncp, kapt, nc, k, g, cell, ccell, acc[ip / 4][ip % 4], Gk);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 7; ++c) Gk[c] = Gc[c];
+          Gk[7] = kq[k];
+        }
+        const T G0 = Gk[0], G1 = Gk[1], G2 = Gk[2], G3 = Gk[3], G4 = Gk[4], G5 = Gk[5], adet = Gk[6];
         const int q = g + 4 * k;
         const T w = s_qw[q];
         const bool qok = valid && q < NQ;
-        const T s = qok ? kq[k] * w : T(0);
+        const T s = qok ? Gk[7] * w : T(0);
         const int i0 = C * k;
         T x, y, z, val = T(0);
         if (BWD) {
@@ -605,7 +654,7 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
 
 // Diagonal and load vector (setup-time work, vector ALUs): one (cell, local
 // node) pair per thread, same slots and fixed-order block reduction.
-template <typename T, int NDOF, int NQ, int MODE>
+template <typename T, int NDOF, int NQ, int MODE, bool CURV>
 __global__ void __launch_bounds__(kThreads) cg_vec_kernel(CGDev d, const T* __restrict__ kappa, T* __restrict__ out) {
   constexpr int NDP = NDOF + 1;
   constexpr int NPT = 4 * ((NQ + 3) / 4);
@@ -627,11 +676,14 @@ __global__ void __launch_bounds__(kThreads) cg_vec_kernel(CGDev d, const T* __re
       const int cl = idx % kBlockCells, j = idx / kBlockCells;
       const int cell = b * kBlockCells + cl;
       if (cell >= nc) continue;
-      const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
-      const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
-      const T adet = geo[6 * ncp + cell];
       T acc = 0;
       for (int q = 0; q < NQ; ++q) {
+        // geometry row (c, q) of curved cells, or row c of straight ones
+        const long gr = CURV ? (long)q * ncp + cell : (long)cell;
+        const long gs = CURV ? (long)NQ * ncp : (long)ncp;
+        const T G0 = geo[gr], G1 = geo[gs + gr], G2 = geo[2 * gs + gr];
+        const T G3 = geo[3 * gs + gr], G4 = geo[4 * gs + gr], G5 = geo[5 * gs + gr];
+        const T adet = geo[6 * gs + gr];
         const T w = qw[q];
         const T c = kappa ? kappa[(long)q * nc + cell] : T(1);
         const T x = s_tab[(q * 4 + 0) * NDP + j], y = s_tab[(q * 4 + 1) * NDP + j];
@@ -679,7 +731,7 @@ hipError_t launch_combine(const CGDev& d, const void* src, void* out, hipStream_
   return hipGetLastError();
 }
 
-template <typename T, int NDOF, int NQ, int C, int MODE, bool BF>
+template <typename T, int NDOF, int NQ, int C, int MODE, bool BF, bool CURV>
 hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void* kappa, void* out, void* dk,
                         hipStream_t s, hipEvent_t* ev) {
   using TL = typename EngineSel<T, NDOF, NQ, C, BF>::type;
@@ -687,7 +739,7 @@ hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void
   const size_t lds = (size_t)TL::LDS_BYTES + (size_t)(TL::NPT + kBlockCells * NDOF + ustage) * sizeof(T) +
                      (size_t)NDOF * kBlockCells * sizeof(uint16_t);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  auto kern = cg_kernel<T, NDOF, NQ, C, MODE, BF>;
+  auto kern = cg_kernel<T, NDOF, NQ, C, MODE, BF, CURV>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
@@ -701,11 +753,11 @@ hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void
   return launch_combine<T, MODE>(d, MODE == MODE_BACKWARD ? g : u, out, s);
 }
 
-template <typename T, int NDOF, int NQ, int MODE>
+template <typename T, int NDOF, int NQ, int MODE, bool CURV>
 hipError_t launch_cg_vec(const CGDev& d, const void* kappa, void* out, hipStream_t s, hipEvent_t* ev) {
   constexpr int NPT = 4 * ((NQ + 3) / 4);
   const size_t lds = (size_t)(NPT * 4 * (NDOF + 1) + kBlockCells * NDOF) * sizeof(T);
-  auto kern = cg_vec_kernel<T, NDOF, NQ, MODE>;
+  auto kern = cg_vec_kernel<T, NDOF, NQ, MODE, CURV>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
@@ -717,24 +769,31 @@ hipError_t launch_cg_vec(const CGDev& d, const void* kappa, void* out, hipStream
   return launch_combine<T, MODE>(d, nullptr, out, s);
 }
 
-template <typename T, int NDOF, int NQ, bool BF>
-hipError_t launch_cg_mode(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
-                          void* dk, hipStream_t s, hipEvent_t* ev, bool* supported) {
+template <typename T, int NDOF, int NQ, bool BF, bool CURV>
+hipError_t launch_cg_geo(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
+                         void* dk, hipStream_t s, hipEvent_t* ev, bool* supported) {
   const bool mass = d.sigma != 0.0;
   switch (mode) {
     case MODE_APPLY:
-      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_APPLY, BF>(d, u, g, kappa, out, dk, s, ev)
-                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_APPLY, BF>(d, u, g, kappa, out, dk, s, ev);
+      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_APPLY, BF, CURV>(d, u, g, kappa, out, dk, s, ev)
+                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_APPLY, BF, CURV>(d, u, g, kappa, out, dk, s, ev);
     case MODE_BACKWARD:
       if (BF) {
         *supported = false;
         return hipSuccess;
       }
-      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_BACKWARD, false>(d, u, g, kappa, out, dk, s, ev)
-                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_BACKWARD, false>(d, u, g, kappa, out, dk, s, ev);
-    case MODE_DIAG: return launch_cg_vec<T, NDOF, NQ, MODE_DIAG>(d, kappa, out, s, ev);
-    default: return launch_cg_vec<T, NDOF, NQ, MODE_LOAD>(d, kappa, out, s, ev);
+      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_BACKWARD, false, CURV>(d, u, g, kappa, out, dk, s, ev)
+                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_BACKWARD, false, CURV>(d, u, g, kappa, out, dk, s, ev);
+    case MODE_DIAG: return launch_cg_vec<T, NDOF, NQ, MODE_DIAG, CURV>(d, kappa, out, s, ev);
+    default: return launch_cg_vec<T, NDOF, NQ, MODE_LOAD, CURV>(d, kappa, out, s, ev);
   }
+}
+
+template <typename T, int NDOF, int NQ, bool BF>
+hipError_t launch_cg_mode(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
+                          void* dk, hipStream_t s, hipEvent_t* ev, bool* supported) {
+  return d.curved ? launch_cg_geo<T, NDOF, NQ, BF, true>(d, mode, u, g, kappa, out, dk, s, ev, supported)
+                  : launch_cg_geo<T, NDOF, NQ, BF, false>(d, mode, u, g, kappa, out, dk, s, ev, supported);
 }
 
 template <typename T, bool BF>

@@ -362,6 +362,8 @@ struct tetmf_op {
   CGDev cg{};
   DGDev dg{};
   double flops = 0, bytes = 0;
+  bool curved = false;
+  const double* qjac = nullptr;  // per-point Jacobians during set-up only (user memory)
   const tetmf_mesh* mesh_tag = nullptr;
   int64_t mesh_nc = 0, mesh_nv = 0;
   // solver scratch (allocated on first solve) and smoother scratch (first smoothing)
@@ -539,6 +541,32 @@ std::vector<double> cell_geometry(const tetmf_mesh& m, const std::vector<int32_t
     const double vals[7] = {G[0][0], G[0][1], G[0][2], G[1][1], G[1][2], G[2][2], adet};
     for (int k = 0; k < 7; ++k) geo[(size_t)k * ncp + i] = vals[k];
   }
+  return geo;
+}
+
+// Per-point geometry of curved cells [7][nq][ncp]: G_q = |det J_q| J_q^-1
+// J_q^-T and |det J_q| for each library cell and rule point, from the user's
+// Jacobians [n_cell][nq][3][3] (user cell order).
+std::vector<double> point_geometry(const double* jac, const std::vector<int32_t>& perm, int nq, int64_t ncp) {
+  std::vector<double> geo((size_t)7 * nq * ncp, 0.0);
+  for (int64_t i = 0; i < (int64_t)perm.size(); ++i)
+    for (int q = 0; q < nq; ++q) {
+      const double* a = &jac[((size_t)perm[i] * nq + q) * 9];
+      M3 J;
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) J.a[r][c] = a[3 * r + c];
+      const double adet = std::fabs(det3(J));
+      M3 Ji = inv3(J);
+      double G[3][3];
+      for (int x = 0; x < 3; ++x)
+        for (int y = 0; y < 3; ++y) {
+          double sum = 0;
+          for (int k = 0; k < 3; ++k) sum += Ji.a[x][k] * Ji.a[y][k];
+          G[x][y] = adet * sum;
+        }
+      const double vals[7] = {G[0][0], G[0][1], G[0][2], G[1][1], G[1][2], G[2][2], adet};
+      for (int k = 0; k < 7; ++k) geo[((size_t)k * nq + q) * ncp + i] = vals[k];
+    }
   return geo;
 }
 
@@ -812,7 +840,9 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
   d.nq = op->nq;
   d.nbd_max = nbd_max;
   d.sigma = op->sigma;
-  d.geo = op->upload_real(cell_geometry(m, perm, op->ncp));
+  d.curved = op->curved ? 1 : 0;
+  d.geo = op->upload_real(op->curved ? point_geometry(op->qjac, perm, op->nq, op->ncp)
+                                     : cell_geometry(m, perm, op->ncp));
   d.blk_priv_start = (const int*)op->upload(priv_start);
   d.blk_npriv = (const int*)op->upload(npriv);
   d.blk_nbd = (const int*)op->upload(blk_nbd);
@@ -975,7 +1005,9 @@ void work_model(tetmf_op* op, const tetmf_mesh& m) {
   const double fcell = 4 * r * nq * nd + cq * nq + nd;
   if (op->kind == TETMF_CG) {
     op->flops = fcell * m.nc;
-    op->bytes = m.nc * ((mass ? 7 : 6) * s + 4 * nd + s * nq) + 2 * s * op->n_dofs;
+    // geometry per cell, or per rule point for curved cells
+    const double ng = (mass ? 7 : 6) * (op->curved ? nq : 1.0);
+    op->bytes = m.nc * (ng * s + 4 * nd + s * nq) + 2 * s * op->n_dofs;
   } else {
     const double nqf = op->nqf;
     const double nbf = (double)(m.nf - m.nif);
@@ -1041,6 +1073,28 @@ int init_op(const tetmf_mesh* mesh, const tetmf_op_desc* d, tetmf_op* op, const 
     if (!(x[0] >= 0 && x[1] >= 0 && x[2] >= 0 && x[0] + x[1] + x[2] <= 1) || !(d->q_weights[q] > 0))
       return fail(TETMF_ERR_INVALID_ARGUMENT, w + ": quadrature point outside the reference cell");
   }
+  if (d->q_jacobians) {
+    if (op->kind != TETMF_CG) return fail(TETMF_ERR_UNSUPPORTED, w + ": curved cells are supported for CG only");
+    for (int64_t e = 0; e < mesh->nc; ++e)
+      for (int q = 0; q < op->nq; ++q) {
+        const double* a = &d->q_jacobians[((size_t)e * op->nq + q) * 9];
+        M3 J;
+        double fro = 0;
+        bool finite = true;
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) {
+            J.a[r][c] = a[3 * r + c];
+            fro += a[3 * r + c] * a[3 * r + c];
+            finite = finite && std::isfinite(a[3 * r + c]);
+          }
+        const double det = finite ? std::fabs(det3(J)) : 0.0;
+        if (!finite || !(det > 1e-12 * fro * std::sqrt(fro)))
+          return fail(TETMF_ERR_DEGENERATE_CELL, w + ": degenerate or non-finite Jacobian at cell " +
+                                                     std::to_string(e) + ", point " + std::to_string(q));
+      }
+    op->curved = true;
+    op->qjac = d->q_jacobians;
+  }
   if (d->ordering == TETMF_ORDER_AS_GIVEN) {
     op->cell_perm.resize(mesh->nc);
     std::iota(op->cell_perm.begin(), op->cell_perm.end(), 0);
@@ -1079,6 +1133,7 @@ extern "C" int tetmf_op_create(const tetmf_mesh* mesh, const tetmf_op_desc* d, t
       setup_dg(op, *mesh, true);
     fill_tables(op, d);
     work_model(op, *mesh);
+    op->qjac = nullptr;
     *out = guard.release();
     return TETMF_OK;
   });
@@ -1297,7 +1352,7 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
     if (op64->kind != TETMF_CG || op64->prec != TETMF_F64)
       return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_solve: op64 must be a CG FP64 operator");
     if (opi && (opi->kind != TETMF_CG || opi->n_dofs != op64->n_dofs || opi->mesh_nc != op64->mesh_nc ||
-                opi->cell_perm != op64->cell_perm || opi->n_free != op64->n_free))
+                opi->cell_perm != op64->cell_perm || opi->n_free != op64->n_free || opi->curved != op64->curved))
       return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_solve: inner operator does not match op64");
     if ((const void*)b == (const void*)x) return fail(TETMF_ERR_ALIAS, "tetmf_solve: b and x alias");
     DeviceScope dsc(op64->device);

@@ -32,7 +32,6 @@ def test_solve_poisson_dirichlet(inner):
     x, st, ok = op.solve(bt, inner=opi, rtol=1e-10)
     assert ok, st
     xs = x.cpu().numpy()
-    r = b[idx] - (A @ xs[np.argsort(idx)])[idx] if False else None
     # true residual with the oracle matrix in oracle order
     xo = np.empty_like(xs)
     xo[idx] = xs

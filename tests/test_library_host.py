@@ -119,3 +119,28 @@ def test_smoother_argument_errors(L):
     lam = ctypes.c_double()
     assert lib.tetmf_chebyshev(None, None, None, None, None, 5, 0.1, 2.0, 1, None) == -1
     assert lib.tetmf_estimate_lambda_max(None, None, None, 10, ctypes.byref(lam), None) == -1
+
+
+def test_curved_setup_checks():
+    """Curved cells: host-side checks of the per-point Jacobians (no GPU)."""
+    import paper_2509_10226_amd as tm
+    xyz, tets = synth.kuhn_cube_mesh(2, 0.1, 0)
+    qp, qw = synth.tet_rule(4)
+    mesh = tm.Mesh(xyz, tets)
+    jac = synth.curved_jacobians(xyz, tets, qp, 0.25)
+    assert tm.check_setup(mesh, 2, (qp, qw), q_jacobians=jac) == tm.check_setup(mesh, 2, (qp, qw))
+    bad = jac.copy()
+    bad[3, 5] = 0.0
+    with pytest.raises(tm.TetmfError) as e:
+        tm.check_setup(mesh, 2, (qp, qw), q_jacobians=bad)
+    assert e.value.status == -2
+    bad = jac.copy()
+    bad[1, 2, 0, 0] = np.nan
+    with pytest.raises(tm.TetmfError):
+        tm.check_setup(mesh, 2, (qp, qw), q_jacobians=bad)
+    fp, fw = synth.tri_rule(4)
+    with pytest.raises(tm.TetmfError) as e:
+        tm.check_setup(mesh, 2, (qp, qw), kind="dg", frule=(fp, fw), q_jacobians=jac)
+    assert e.value.status == -4
+    with pytest.raises(ValueError):
+        tm.check_setup(mesh, 2, (qp, qw), q_jacobians=jac[:, :3])
