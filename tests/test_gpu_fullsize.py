@@ -3,7 +3,8 @@ times, on outputs the oracle can compute one by one:
 
 * CG P3, 64^3 x 6 cells, lognormal(0, 1) coefficient: sampled rows of the
   FP64 / FP32 / BF16-operand apply against oracle rows (only the cells around
-  each sampled DoF are assembled);
+  each sampled DoF are assembled), and of the FP64 / FP32 apply on curved
+  cells (the same mesh through a smooth map, a Jacobian per rule point);
 * SIPG P3, 32^3 x 6 cells, lognormal(0, 0.5) cell and face coefficients,
   Dirichlet mirror: the rows of sampled cells;
 * CG P2 Helmholtz (stiffness + 1.0 mass), 48^3 x 6 cells: backward -- sampled
@@ -94,6 +95,37 @@ def test_c3_sampled_rows(c3, precision, tol):
                              kappa=c3["kap"])
     err = np.abs(v[rows] - y) / scale
     print(f"C3 {precision}: max row error / sum|a u| = {err.max():.3e}")
+    assert err.max() <= tol
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_f3_curved_sampled_rows(c3, precision, tol):
+    """The same workload on curved cells (per-point Jacobians of the smooth
+    map of synth.curved_jacobians, as bench.py --config f3 runs it)."""
+    tm = c3["tm"]
+    jac = synth.curved_jacobians(c3["xyz"], c3["tets"], c3["qp"], 0.25)
+    op = tm.Operator(c3["mesh"], 3, (c3["qp"], c3["qw"]), precision=precision, q_jacobians=jac)
+    _, dof_xyz, dof_cell = op.numbering()
+    kl = op.cell_data_to_library(torch.from_numpy(c3["kap"]).to(DEV))
+    u = synth.uniform(1, synth.STREAM_U, op.n_dofs)
+    if precision != "f64":
+        u = u.astype(np.float32).astype(np.float64)
+    v = op.apply(torch.from_numpy(u).to(DEV, op.dtype), kl).double().cpu().numpy()
+    rows = np.random.default_rng(43).choice(op.n_dofs, 48, replace=False)
+    tree = cKDTree(dof_xyz)
+    cells = dof_cell[rows]
+    locs = oracle_local_node(c3["xyz"], c3["tets"], cells, dof_xyz[rows], 3)
+    keys, orows = oracle.cg_rows(c3["xyz"], c3["tets"], 3, c3["qp"], c3["qw"], cells, locs, kappa=c3["kap"],
+                                 jac=jac)
+    y, scale = [], []
+    for row in orows:
+        ck = list(row.keys())
+        cols = tree.query(key_coords(ck, c3["xyz"], 3))[1]
+        coef = np.array([row[k] for k in ck])
+        y.append(float(coef @ u[cols]))
+        scale.append(float(np.abs(coef) @ np.abs(u[cols])))
+    err = np.abs(v[rows] - np.array(y)) / np.array(scale)
+    print(f"F3 curved {precision}: max row error / sum|a u| = {err.max():.3e}")
     assert err.max() <= tol
 
 
