@@ -29,5 +29,6 @@ from .basis import nodes, eval_basis  # noqa: F401
 from .mesh import Geometry, cg_dofs, find_faces  # noqa: F401
 from .smoother import chebyshev  # noqa: F401
 from .assemble import (  # noqa: F401
-    assemble_cg, assemble_dg, cg_kappa_grad, dg_kappa_grad, load_vector, cg_rows, dg_rows,
+    assemble_cg, assemble_dg, cg_kappa_grad, dg_kappa_grad, load_vector, cg_rows, dg_rows, vector_operator,
+    vector_kappa_grad,
 )

@@ -383,3 +383,19 @@ def dg_rows(xyz, tets, p, qpts, qw, fpts, fw, cells_sel, kappa_cell=None, kappa_
                       shape=(sel.size * nd, nc * nd))
     R.sum_duplicates()
     return R
+
+
+def vector_operator(A, n_components):
+    """The operator of a vector-valued problem without coupling between the
+    components (the vector Poisson/Helmholtz problem of Sec. 3.2 and the
+    remark after it): one copy of the scalar operator per component, for
+    vectors stored component by component, u = [u_1; u_2; ...; u_d].  With a
+    Dirichlet scalar operator every component is constrained the same way."""
+    return sp.block_diag([A] * n_components, format="csr")
+
+
+def vector_kappa_grad(grad_fn, u, g, n_components, n_dofs):
+    """d(g^T A(kappa) u)/d kappa for the vector operator: the sum over the
+    components of the scalar gradient (grad_fn(u_c, g_c))."""
+    return sum(grad_fn(u[c * n_dofs:(c + 1) * n_dofs], g[c * n_dofs:(c + 1) * n_dofs])
+               for c in range(n_components))
