@@ -333,6 +333,48 @@ def bench_f1(args):
           flush=True)
 
 
+def bench_f2(args):
+    """Vector-valued Poisson (3 components without coupling, Sec. 3.2): one
+    components-batched apply against three scalar applies of the same
+    operator, CG P3 on the measured workload's mesh, straight-sided and
+    curved cells, FP64 and FP32."""
+    import torch
+
+    import paper_2509_10226_amd as tm
+    import synth
+    xyz, tets, qp, qw, kap = build_workload(args.n)
+    jac = synth.curved_jacobians(xyz, tets, qp, 0.25)
+    mesh = tm.Mesh(xyz, tets)
+    res = {}
+    for geom in ("straight", "curved"):
+        for prec in ("f64", "f32"):
+            qj = jac if geom == "curved" else None
+            opv = tm.Operator(mesh, 3, (qp, qw), precision=prec, q_jacobians=qj, n_components=3)
+            kl = opv.cell_data_to_library(torch.from_numpy(kap).cuda())
+            g = torch.Generator(device="cpu").manual_seed(2)
+            u = (torch.rand(opv.n_vec, generator=g, dtype=torch.float64) * 2 - 1).to("cuda", opv.dtype)
+            ms_v, k_v, _ = time_gpu(opv, kl, u, args.steps, args.warmup)
+            rv = roofline(opv, prec, k_v, traffic_key="vector")
+            del opv
+            ops = tm.Operator(mesh, 3, (qp, qw), precision=prec, q_jacobians=qj)
+            n = ops.n_dofs
+            outs = [torch.empty(n, dtype=ops.dtype, device="cuda") for _ in range(3)]
+
+            def three():
+                for c in range(3):
+                    ops.apply(u[c * n:(c + 1) * n], kl, out=outs[c])
+            ms_s = _time_call(three, args.steps, args.warmup)
+            del ops
+            res[f"{geom}_{prec}"] = {"DoFs_per_s": round(3 * n / (ms_v * 1e-3), 1), "ms_per_step": round(ms_v, 5),
+                                     "kernel_ms": round(k_v, 5), "ms_three_scalar_applies": round(ms_s, 5),
+                                     "speedup_vs_three_scalar": round(ms_s / ms_v, 3), "roofline": rv}
+    print(json.dumps({"metric": "DoFs/s per vector operator apply (3 components), CG P3, components-batched",
+                      "value": res["straight_f64"]["DoFs_per_s"], "unit": "DoFs/s", "dtype": "f64",
+                      "config": {"workload": f"vector Poisson, 3 components, CG P3, {args.n}^3x6 Kuhn tets, "
+                                             "lognormal(0,1) kappa, 24-point rule; curved: the f3 map"},
+                      "variants": res}), flush=True)
+
+
 def bench_f3(args):
     """Curved cells (a Jacobian per rule point, Sec. 3.2): the measured
     workload's mesh pushed through a smooth global map, CG P3 with the
@@ -410,8 +452,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=64, help="cubes per axis (64 = the measured workload)")
     ap.add_argument("--precisions", default="f64,f32,bf16in")
-    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5", "order", "f1", "f3", "f4"],
-                    help="c3 (default): the measured workload; c2/c4/c5/order/f1/f3/f4: secondary measurements, "
+    ap.add_argument("--config", default="c3", choices=["c3", "c2", "c4", "c5", "order", "f1", "f2", "f3", "f4"],
+                    help="c3 (default): the measured workload; c2/c4/c5/order/f1/f2/f3/f4: secondary measurements, "
                          "each printed as its own JSON line")
     ap.add_argument("--order-variant", default="all",
                     choices=["all", "native_locality", "shuffled_locality", "shuffled_as_given"])
@@ -430,7 +472,7 @@ def main():
         return
     if args.config != "c3":
         {"c2": bench_c2, "c4": bench_c4, "c5": bench_c5, "order": bench_order, "f1": bench_f1,
-         "f3": bench_f3, "f4": bench_f4}[args.config](args)
+         "f2": bench_f2, "f3": bench_f3, "f4": bench_f4}[args.config](args)
         return
     dev = torch.device("cuda", 0)
     xyz, tets, qp, qw, kap = build_workload(args.n)

@@ -99,6 +99,14 @@ typedef struct {
    * connectivity and tetmf_op_numbering's coordinates.  DG: UNSUPPORTED.
    * DEGENERATE_CELL when some |det J_q| <= 1e-12 |J_q|_F^3 or is not finite. */
   const double* q_jacobians;
+  /* Components of the field (Sec. 3.2, vector-valued problems without
+   * coupling between the components): 0 or 1 scalar; 3 a vector field, CG in
+   * F64 or F32 only (else UNSUPPORTED).  Every vector of the operator then
+   * holds the components one after another, [n_components][n_dofs], and
+   * A acts on each with the same coefficient; the kappa gradient of the
+   * backward is the sum over the components.  tetmf_load_vector is
+   * UNSUPPORTED for vector fields. */
+  int32_t n_components;
 } tetmf_op_desc;
 
 typedef struct {
@@ -112,6 +120,7 @@ typedef struct {
   double flops_per_apply;  /* algorithmic work of one apply (method's count) */
   double bytes_per_apply;  /* algorithmic HBM bytes of one apply */
   int64_t device_bytes;    /* device memory held by the op */
+  int32_t n_components;    /* 1, or 3 for a vector field (vectors hold n_components * n_dofs values) */
 } tetmf_info;
 
 /* Mesh setup (Sec. 2.2 geometry; faces for eq. (7)).
@@ -160,7 +169,7 @@ int tetmf_cell_data_layout(const tetmf_op* op, const void* src, void* dst, int t
 
 /* v = A(kappa) u  (eq. (5) CG / eq. (7) DG), deterministic: the result is
  * bitwise reproducible for fixed inputs.
- *  u, v: device [n_dofs] in the op precision (FP32 for BF16IN); must not
+ *  u, v: device [n_components * n_dofs] in the op precision (FP32 for BF16IN); must not
  *        alias (ALIAS).
  *  kappa_cell: device [n_q][n_cell] or NULL (kappa = 1).
  *  kappa_face: DG only, device [n_qf][n_face] or NULL (kappa = 1).
@@ -185,7 +194,7 @@ int tetmf_apply_backward(tetmf_op* op, const void* u, const void* g, const void*
                          const void* kappa_face, void* du, void* dkappa_cell, void* dkappa_face,
                          void* stream);
 
-/* d = diag(A(kappa)) (CG), constrained entries 1.  Device [n_dofs]. */
+/* d = diag(A(kappa)) (CG), constrained entries 1.  Device [n_components * n_dofs]. */
 int tetmf_diagonal(tetmf_op* op, const void* kappa_cell, const void* kappa_face, void* d, void* stream);
 
 /* Load vector b_i = sum_e sum_q w_q |det J| f_{e,q} phi_i(x_q) (CG), zero on
@@ -213,7 +222,7 @@ typedef struct {
  *  the FP64 residual r = b - A64 x, an inner Jacobi-PCG on A_inner d = r in
  *  the inner precision (dot products accumulated in FP64), and x += d in
  *  FP64 (mixed precision as in Sec. 4.1).
- *  b, x: device FP64 [n_dofs]; x holds x0 on entry (warm start) and the
+ *  b, x: device FP64 [n_components * n_dofs]; x holds x0 on entry (warm start) and the
  *  solution on exit.  kappa: device [n_q][n_cell] for each op's precision or
  *  NULL.  Synchronises the stream.  Returns NOT_CONVERGED when the caps are
  *  reached. */
@@ -234,8 +243,8 @@ int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* op_inner, const v
  * The error x* - x is multiplied by p(D^-1 A) with
  * p(t) = T_degree((theta - t) / delta) / T_degree(theta / delta); one
  * operator application per step (degree - 1 with zero_guess).
- *  inv_diag: device [n_dofs], 1 / tetmf_diagonal (constrained entries 1).
- *  b: device [n_dofs]; x: device [n_dofs], x_0 on entry unless zero_guess,
+ *  inv_diag: device [n_components * n_dofs], 1 / tetmf_diagonal (constrained entries 1).
+ *  b, x: device [n_components * n_dofs], x_0 on entry unless zero_guess,
  *  the smoothed vector on exit.  All in the op precision (FP32 for BF16IN).
  *  kappa_cell as for tetmf_apply.
  *  degree >= 1, 0 <= lambda_min < lambda_max (INVALID_ARGUMENT otherwise);

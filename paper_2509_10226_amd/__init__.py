@@ -39,7 +39,7 @@ class OpDesc(ctypes.Structure):
         ("n_q", ctypes.c_int32), ("q_points", ctypes.c_void_p), ("q_weights", ctypes.c_void_p),
         ("n_qf", ctypes.c_int32), ("qf_points", ctypes.c_void_p), ("qf_weights", ctypes.c_void_p),
         ("sigma", ctypes.c_double), ("eta", ctypes.c_double), ("device", ctypes.c_int32),
-        ("q_jacobians", ctypes.c_void_p),
+        ("q_jacobians", ctypes.c_void_p), ("n_components", ctypes.c_int32),
     ]
 
 
@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("n_blocks", ctypes.c_int64), ("n_shared", ctypes.c_int64), ("n_partials", ctypes.c_int64),
         ("flops_per_apply", ctypes.c_double), ("bytes_per_apply", ctypes.c_double),
-        ("device_bytes", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64), ("n_components", ctypes.c_int32),
     ]
 
 
@@ -175,7 +175,7 @@ class Mesh:
 
 
 def _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, device, mesh=None,
-               q_jacobians=None):
+               q_jacobians=None, n_components=1):
     qp, qw = (np.ascontiguousarray(a, dtype=np.float64) for a in qrule)
     d = OpDesc()
     d.kind = _KIND[kind]
@@ -196,6 +196,7 @@ def _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, 
     d.sigma = float(sigma)
     d.eta = float(eta)
     d.device = int(device)
+    d.n_components = int(n_components)
     if q_jacobians is not None:
         jac = np.ascontiguousarray(q_jacobians, dtype=np.float64)
         if jac.shape != (mesh.tets.shape[0], qw.size, 3, 3):
@@ -206,10 +207,11 @@ def _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, 
 
 
 def check_setup(mesh, degree, qrule, kind="cg", frule=None, precision="f64", bc="neumann", sigma=0.0, eta=1.0,
-                ordering="locality", q_jacobians=None):
+                ordering="locality", q_jacobians=None, n_components=1):
     """Host-only run of the operator set-up with its invariant checks (no GPU
     needed); returns (n_dofs, n_free) or raises TetmfError."""
-    d, keep = _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, 0, mesh, q_jacobians)
+    d, keep = _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, 0, mesh, q_jacobians,
+                         n_components)
     nd, nf = ctypes.c_int64(), ctypes.c_int64()
     _check(lib().tetmf_op_check(mesh._h, ctypes.byref(d), ctypes.byref(nd), ctypes.byref(nf)))
     del keep
@@ -220,12 +222,14 @@ class Operator:
     """Matrix-free operator A(kappa) on a mesh (see include/tetmf.h)."""
 
     def __init__(self, mesh, degree, qrule, kind="cg", frule=None, precision="f64", bc="neumann",
-                 sigma=0.0, eta=1.0, ordering="locality", device=0, q_jacobians=None):
+                 sigma=0.0, eta=1.0, ordering="locality", device=0, q_jacobians=None, n_components=1):
         """q_jacobians: None (straight-sided cells) or [n_cell, n_q, 3, 3]
-        Jacobians of curved cells at the rule points (tetmf_op_desc)."""
+        Jacobians of curved cells at the rule points; n_components: 1, or 3
+        for a vector field whose vectors hold the components one after
+        another (tetmf_op_desc)."""
         L = lib()
         d, keep = _make_desc(degree, qrule, kind, frule, precision, bc, sigma, eta, ordering, device, mesh,
-                             q_jacobians)
+                             q_jacobians, n_components)
         h = ctypes.c_void_p()
         _check(L.tetmf_op_create(mesh._h, ctypes.byref(d), ctypes.byref(h)))
         del keep
@@ -236,6 +240,8 @@ class Operator:
         _check(L.tetmf_op_info(h, ctypes.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in Info._fields_}
         self.n_dofs = self.info["n_dofs"]
+        self.n_components = max(1, self.info["n_components"])
+        self.n_vec = self.n_dofs * self.n_components  # length of the operator's vectors
         self.n_free = self.info["n_free"]
         self.n_cell = self.info["n_cell"]
         self.n_face = self.info["n_face"]
@@ -284,11 +290,11 @@ class Operator:
     def apply(self, u, kappa_cell=None, kappa_face=None, out=None):
         torch = _torch()
         if out is None:
-            out = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_apply(self._h, _ptr(u, self.dtype, self.n_dofs, "u"),
+            out = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
+        _check(lib().tetmf_apply(self._h, _ptr(u, self.dtype, self.n_vec, "u"),
                                  _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
                                  _ptr(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
-                                 _ptr(out, self.dtype, self.n_dofs, "v"), _stream()))
+                                 _ptr(out, self.dtype, self.n_vec, "v"), _stream()))
         return out
 
     def backward(self, u, g, kappa_cell=None, need_du=True, need_dkappa=True, kappa_face=None,
@@ -298,11 +304,11 @@ class Operator:
         operator with need_dkappa_face, (du, dkappa_cell, dkappa_face)."""
         torch = _torch()
         dev = self._device()
-        du = torch.empty(self.n_dofs, dtype=self.dtype, device=dev) if need_du else None
+        du = torch.empty(self.n_vec, dtype=self.dtype, device=dev) if need_du else None
         dk = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=dev) if need_dkappa else None
         dkf = torch.empty((self.n_qf, self.n_face), dtype=self.dtype, device=dev) if need_dkappa_face else None
-        _check(lib().tetmf_apply_backward(self._h, _ptr(u, self.dtype, self.n_dofs, "u"),
-                                          _ptr(g, self.dtype, self.n_dofs, "g"),
+        _check(lib().tetmf_apply_backward(self._h, _ptr(u, self.dtype, self.n_vec, "u"),
+                                          _ptr(g, self.dtype, self.n_vec, "g"),
                                           _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
                                           _ptr(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
                                           _ptr(du), _ptr(dk), _ptr(dkf), _stream()))
@@ -310,7 +316,7 @@ class Operator:
 
     def diagonal(self, kappa_cell=None):
         torch = _torch()
-        d = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
+        d = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
         _check(lib().tetmf_diagonal(self._h, _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
                                     None, _ptr(d), _stream()))
         return d
@@ -326,14 +332,14 @@ class Operator:
               max_outer=50, max_inner=5000, precond="jacobi"):
         """Solve A x = b (see tetmf_solve).  Returns (x, stats dict, converged)."""
         torch = _torch()
-        x = torch.zeros(self.n_dofs, dtype=torch.float64, device=self._device()) if x0 is None else x0.clone()
+        x = torch.zeros(self.n_vec, dtype=torch.float64, device=self._device()) if x0 is None else x0.clone()
         o = SolveOpts(rtol, inner_rtol, max_outer, max_inner, 1 if precond == "jacobi" else 0)
         st = SolveStats()
         status = _check(lib().tetmf_solve(
             self._h, _ptr(kappa, torch.float64, self.n_q * self.n_cell, "kappa"),
             inner._h if inner is not None else None,
             _ptr(kappa_inner, inner.dtype if inner is not None else None, None, "kappa_inner"),
-            _ptr(b, torch.float64, self.n_dofs, "b"), _ptr(x, torch.float64, self.n_dofs, "x"),
+            _ptr(b, torch.float64, self.n_vec, "b"), _ptr(x, torch.float64, self.n_vec, "x"),
             ctypes.byref(o), ctypes.byref(st), _stream()))
         stats = {k: getattr(st, k) for k, _ in SolveStats._fields_}
         return x, stats, status == 0
@@ -345,10 +351,10 @@ class Operator:
         torch = _torch()
         zero = x is None
         if zero:
-            x = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
+            x = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
         _check(lib().tetmf_chebyshev(self._h, _ptr(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
-                                     _ptr(inv_diag, self.dtype, self.n_dofs, "inv_diag"),
-                                     _ptr(b, self.dtype, self.n_dofs, "b"), _ptr(x, self.dtype, self.n_dofs, "x"),
+                                     _ptr(inv_diag, self.dtype, self.n_vec, "inv_diag"),
+                                     _ptr(b, self.dtype, self.n_vec, "b"), _ptr(x, self.dtype, self.n_vec, "x"),
                                      int(degree), float(lambda_min), float(lambda_max), 1 if zero else 0, _stream()))
         return x
 
@@ -357,7 +363,7 @@ class Operator:
         tetmf_estimate_lambda_max)."""
         lam = ctypes.c_double()
         _check(lib().tetmf_estimate_lambda_max(self._h, _ptr(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
-                                               _ptr(inv_diag, self.dtype, self.n_dofs, "inv_diag"), int(n_iter),
+                                               _ptr(inv_diag, self.dtype, self.n_vec, "inv_diag"), int(n_iter),
                                                ctypes.byref(lam), _stream()))
         return lam.value
 

@@ -29,6 +29,8 @@ struct CGDev {
   int nq;                 // quadrature points (<= 4 * MT of the kernel)
   int nbd_max;            // largest number of DoFs of one block
   int curved;             // geo holds one entry per rule point (see geo)
+  int ncomp;              // components of the vector field (1: scalar), stored one after another
+  int n_partials;         // partial sums per component
   double sigma;           // mass coefficient
   const void* geo;        // [7][ncp]: G00 G01 G02 G11 G12 G22 (= |detJ| J^-1 J^-T), |detJ|;
                           // curved: [7][nq][ncp], the same per rule point

@@ -373,8 +373,7 @@ __device__ inline int phase_tid() {
 // Sum the slots of every block DoF (fixed order) and store them.
 template <typename T>
 __device__ inline void cg_reduce(const CGDev& d, const T* __restrict__ s_slot, int nbd, int npriv, int ps, int oo,
-                                 int po, T* __restrict__ out) {
-  T* partials = static_cast<T*>(d.partials);
+                                 int po, T* __restrict__ out, T* __restrict__ partials) {
   const int nother = nbd - npriv;
   for (int k0 = 0; k0 < nbd; k0 += kStageUnroll * kThreads) {
     int p0[kStageUnroll], p1[kStageUnroll], dst[kStageUnroll];
@@ -423,7 +422,11 @@ __device__ inline void point_geo(const T* __restrict__ geo, int ncp, const T* __
   G[7] = kappa ? load_at(kappa + (long)(4 * k) * nc, kof) : T(1);
 }
 
-template <typename T, int NDOF, int NQ, int C, int MODE, bool BF, bool CURV>
+// NCOMP > 1: a vector field of NCOMP components without coupling (Sec. 3.2),
+// stored component by component; each block stages its local indices once
+// and runs stage / tiles / reduce per component (the LDS holds one
+// component at a time), re-reading the cell data from cache.
+template <typename T, int NDOF, int NQ, int C, int MODE, bool BF, bool CURV, int NCOMP>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* __restrict__ kappa,
           T* __restrict__ out, T* __restrict__ dk) {
@@ -450,205 +453,228 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
   for (int b = first; b < last; b += stride) {
     const int nbd = d.blk_nbd[b], npriv = d.blk_npriv[b], ps = d.blk_priv_start[b];
     const int oo = d.blk_other_off[b], po = d.blk_ptr_off[b];
-    __syncthreads();  // previous block's slots, staged values and indices are consumed
-    {
-      // curved cells: thread index re-derived per block, so that the staging
-      // addresses are not kept live across the compute phase (which needs
-      // the registers for the per-point geometry; the straight kernels are
-      // faster with them kept)
-      const unsigned st = CURV ? (unsigned)phase_tid() : threadIdx.x;
-      // block-local indices: [NDOF][kBlockCells] uint16, copied as 32-bit words
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(d.lidx);
-      uint32_t* dstw = reinterpret_cast<uint32_t*>(s_lidx);
-      constexpr int W = NDOF * kBlockCells / 2;
-      uint32_t wv[(W + kThreads - 1) / kThreads];
+    // one pass per component (a scalar field: one pass with comp = 0)
+    auto comp_pass = [&](const int comp) {
+      const T* uc = u + (long)comp * d.n_dofs;
+      const T* gc = BWD ? gin + (long)comp * d.n_dofs : gin;
+      T* oc = write_out ? out + (long)comp * d.n_dofs : out;
+      __syncthreads();  // previous block's (component's) slots, staged values and indices are consumed
+      {
+        // curved cells: thread index re-derived per block, so that the staging
+        // addresses are not kept live across the compute phase (which needs
+        // the registers for the per-point geometry; the straight kernels are
+        // faster with them kept)
+        const unsigned st = CURV ? (unsigned)phase_tid() : threadIdx.x;
+        // block-local indices: [NDOF][kBlockCells] uint16, copied as 32-bit words
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(d.lidx);
+        uint32_t* dstw = reinterpret_cast<uint32_t*>(s_lidx);
+        constexpr int W = NDOF * kBlockCells / 2;
+        uint32_t wv[(W + kThreads - 1) / kThreads];
+        if (comp == 0) {
 #pragma unroll
-      for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
-        const int w = i * kThreads + st;
-        const int j = (2 * w) / kBlockCells, cl = (2 * w) % kBlockCells;
-        wv[i] = w < W ? src[((long)j * ncp + (long)b * kBlockCells + cl) / 2] : 0u;
-      }
-      // DoF values: all index loads first, then all value loads (clamped
-      // indices keep every load in bounds, so no load needs a branch; the
-      // other-DoF lists carry one padding entry for blocks without any)
-      const int nother = nbd - npriv;
-      for (int k0 = 0; k0 < nbd; k0 += kStageUnroll * kThreads) {
-        int gi[kStageUnroll];
-        bool ok[kStageUnroll];
-#pragma unroll
-        for (int i = 0; i < kStageUnroll; ++i) {
-          const int k = k0 + i * kThreads + st;
-          const int oi = min(max(k - npriv, 0), max(nother - 1, 0));
-          const int og = d.other_gid[oo + oi];
-          gi[i] = (k < npriv) ? ps + k : og;
-          ok[i] = k < nbd && (k < npriv || og < d.n_free);
+          for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
+            const int w = i * kThreads + st;
+            const int j = (2 * w) / kBlockCells, cl = (2 * w) % kBlockCells;
+            wv[i] = w < W ? src[((long)j * ncp + (long)b * kBlockCells + cl) / 2] : 0u;
+          }
         }
-        T uv[kStageUnroll], gv[kStageUnroll];
+        // DoF values: all index loads first, then all value loads (clamped
+        // indices keep every load in bounds, so no load needs a branch; the
+        // other-DoF lists carry one padding entry for blocks without any)
+        const int nother = nbd - npriv;
+        for (int k0 = 0; k0 < nbd; k0 += kStageUnroll * kThreads) {
+          int gi[kStageUnroll];
+          bool ok[kStageUnroll];
 #pragma unroll
-        for (int i = 0; i < kStageUnroll; ++i) {
-          const int src_i = ok[i] ? gi[i] : 0;
-          uv[i] = u[src_i];
-          if (BWD) gv[i] = gin[src_i];
-          uv[i] = ok[i] ? uv[i] : T(0);
-          if (BWD) gv[i] = ok[i] ? gv[i] : T(0);
+          for (int i = 0; i < kStageUnroll; ++i) {
+            const int k = k0 + i * kThreads + st;
+            const int oi = min(max(k - npriv, 0), max(nother - 1, 0));
+            const int og = d.other_gid[oo + oi];
+            gi[i] = (k < npriv) ? ps + k : og;
+            ok[i] = k < nbd && (k < npriv || og < d.n_free);
+          }
+          T uv[kStageUnroll], gv[kStageUnroll];
+#pragma unroll
+          for (int i = 0; i < kStageUnroll; ++i) {
+            const int src_i = ok[i] ? gi[i] : 0;
+            uv[i] = uc[src_i];
+            if (BWD) gv[i] = gc[src_i];
+            uv[i] = ok[i] ? uv[i] : T(0);
+            if (BWD) gv[i] = ok[i] ? gv[i] : T(0);
+          }
+#pragma unroll
+          for (int i = 0; i < kStageUnroll; ++i) {
+            const int k = k0 + i * kThreads + st;
+            if (k < nbd) {
+              s_u[k] = uv[i];
+              if (BWD) s_u[d.nbd_max + k] = gv[i];
+            }
+          }
         }
+        if (comp == 0) {
 #pragma unroll
-        for (int i = 0; i < kStageUnroll; ++i) {
-          const int k = k0 + i * kThreads + st;
-          if (k < nbd) {
-            s_u[k] = uv[i];
-            if (BWD) s_u[d.nbd_max + k] = gv[i];
+          for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
+            const int w = i * kThreads + st;
+            if (w < W) dstw[w] = wv[i];
           }
         }
       }
-#pragma unroll
-      for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
-        const int w = i * kThreads + st;
-        if (w < W) dstw[w] = wv[i];
-      }
-    }
-    __syncthreads();
+      __syncthreads();
 #pragma unroll 1
-    for (int tt = 0; tt < kTilesPerWave; ++tt) {
-      // lane coordinates re-derived per tile (not held across the block loop)
-      const int tid = phase_tid();
-      const int lane = tid & 63, wave = tid >> 6;
-      const int g = lane >> 4, c16 = lane & 15;
-      const int cl = (wave + tt * kWaves) * kTile + c16;
-      const int cell = b * kBlockCells + cl;
-      const bool valid = cell < nc;
-      // per-cell arrays: row base (uniform) + 32-bit lane offset
-      // straight cells: G and |det J| of the cell (curved: per point below)
-      T Gc[7];
-      if constexpr (!CURV) {
-        const uint32_t coff = (uint32_t)cell * (uint32_t)sizeof(T);
+      for (int tt = 0; tt < kTilesPerWave; ++tt) {
+        // lane coordinates re-derived per tile (not held across the block loop)
+        const int tid = phase_tid();
+        const int lane = tid & 63, wave = tid >> 6;
+        const int g = lane >> 4, c16 = lane & 15;
+        const int cl = (wave + tt * kWaves) * kTile + c16;
+        const int cell = b * kBlockCells + cl;
+        const bool valid = cell < nc;
+        // per-cell arrays: row base (uniform) + 32-bit lane offset
+        // straight cells: G and |det J| of the cell (curved: per point below)
+        T Gc[7];
+        if constexpr (!CURV) {
+          const uint32_t coff = (uint32_t)cell * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) Gc[c] = load_at(geo + c * (long)ncp, coff);
-        Gc[6] = (C == 4) ? load_at(geo + 6 * (long)ncp, coff) : T(0);
-      }
-      // coefficient at this lane's points q = g + 4k (row q of [NQ][nc]),
-      // from a clamped (always valid) address and masked afterwards
-      T kq[KP];
-      if (CURV) {
-        // loaded with the per-point geometry
-      } else if (kappa) {
-        const int cc = valid ? cell : nc - 1;
-        const uint32_t kof = ((uint32_t)g * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T);
+          for (int c = 0; c < 6; ++c) Gc[c] = load_at(geo + c * (long)ncp, coff);
+          Gc[6] = (C == 4) ? load_at(geo + 6 * (long)ncp, coff) : T(0);
+        }
+        // coefficient at this lane's points q = g + 4k (row q of [NQ][nc]),
+        // from a clamped (always valid) address and masked afterwards
+        T kq[KP];
+        if (CURV) {
+          // loaded with the per-point geometry
+        } else if (kappa) {
+          const int cc = valid ? cell : nc - 1;
+          const uint32_t kof = ((uint32_t)g * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T);
+#pragma unroll
+          for (int k = 0; k < KP; ++k) {
+            if (4 * k + 3 < NQ) {
+              kq[k] = load_at(kappa + (long)(4 * k) * nc, kof);
+            } else {
+              const int q = min(g + 4 * k, NQ - 1);
+              kq[k] = load_at(kappa, ((uint32_t)q * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T));
+            }
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < KP; ++k) kq[k] = T(1);
+        }
+        uint16_t pv[4 + TL::NVA];
+        if (write_out) {
+          // row(g, r) = row(g, 0) + row(0, r): lane part and uniform part
+          const uint32_t pof = ((uint32_t)M::row(g, 0) * (uint32_t)ncp + (uint32_t)cell) * 2u;
+#pragma unroll
+          // rows beyond the cell's DoFs (fewer than 16 at p <= 2) have no slot
+          for (int r = 0; r < 4; ++r)
+            pv[r] = (TL::NMF == 16 || M::row(g, r) < TL::NMF) ? load_at(d.pos + (long)M::row(0, r) * ncp, pof)
+                                                               : uint16_t(0);
+          if (TL::NVA > 0)
+            pv[4] = load_at(d.pos + 16 * (long)ncp,
+                            ((uint32_t)min(g, TL::NVA - 1) * (uint32_t)ncp + (uint32_t)cell) * 2u);
+        }
+        T ub[NB];
+        T gb[BWD ? NB : 1];
+#pragma unroll
+        for (int ks = 0; ks < NB; ++ks) {
+          const int j = TL::bdof(g, ks);
+          const int l = j < NDOF ? s_lidx[j * kBlockCells + cl] : 0;
+          ub[ks] = j < NDOF ? s_u[l] : T(0);
+          if (BWD) gb[BWD ? ks : 0] = j < NDOF ? s_u[d.nbd_max + l] : T(0);
+        }
+        acc_t acc[MT];
+        TL::interpolate(s_eng, ub, g, c16, acc);
+        acc_t accg[BWD ? MT : 1];
+        if (BWD) {
+          T gtmp[NB];
+#pragma unroll
+          for (int ks = 0; ks < NB; ++ks) gtmp[ks] = gb[BWD ? ks : 0];
+          acc_t tmp[MT];
+          TL::interpolate(s_eng, gtmp, g, c16, tmp);
+#pragma unroll
+          for (int t = 0; t < MT; ++t) accg[BWD ? t : 0] = tmp[t];
+        }
+        // point operator D in registers: item s = C k + c at acc[s / 4][s % 4].
+        // Curved cells: the geometry of point k + 1 is requested once point
+        // k - 1 is done (two points' geometry live at a time).
+        const int ccell = valid ? cell : nc - 1;
+        // per-tile copies of the bases, so that the row addresses derived from
+        // them are not hoisted out of the block loop (36 of them at P3)
+        const T* geot = geo;
+        const T* kapt = kappa;
+        if constexpr (CURV) asm volatile("" : "+s"(geot), "+s"(kapt));
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
-          if (4 * k + 3 < NQ) {
-            kq[k] = load_at(kappa + (long)(4 * k) * nc, kof);
+          T Gk[8];
+          if constexpr (CURV) {
+            const int ip = C * (k > 0 ? k - 1 : 0);
+            point_geo<T, NQ, C>(geot, ncp, kapt, nc, k, g, cell, ccell, acc[ip / 4][ip % 4], Gk);
           } else {
-            const int q = min(g + 4 * k, NQ - 1);
-            kq[k] = load_at(kappa, ((uint32_t)q * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T));
+#pragma unroll
+            for (int c = 0; c < 7; ++c) Gk[c] = Gc[c];
+            Gk[7] = kq[k];
           }
+          const T G0 = Gk[0], G1 = Gk[1], G2 = Gk[2], G3 = Gk[3], G4 = Gk[4], G5 = Gk[5], adet = Gk[6];
+          const int q = g + 4 * k;
+          const T w = s_qw[q];
+          const bool qok = valid && q < NQ;
+          const T s = qok ? Gk[7] * w : T(0);
+          const int i0 = C * k;
+          T x, y, z, val = T(0);
+          if (BWD) {
+            const T ux = acc[(i0) / 4][(i0) % 4], uy = acc[(i0 + 1) / 4][(i0 + 1) % 4];
+            const T uz = acc[(i0 + 2) / 4][(i0 + 2) % 4];
+            x = accg[BWD ? (i0) / 4 : 0][(i0) % 4];
+            y = accg[BWD ? (i0 + 1) / 4 : 0][(i0 + 1) % 4];
+            z = accg[BWD ? (i0 + 2) / 4 : 0][(i0 + 2) % 4];
+            if constexpr (C == 4) val = accg[BWD ? (i0 + 3) / 4 : 0][(i0 + 3) % 4];
+            // dkappa = w_q grad_ref(u)^T G grad_ref(g)  (G already holds |det J|)
+            const T dkv = w * (ux * (G0 * x + G1 * y + G2 * z) + uy * (G1 * x + G3 * y + G4 * z) +
+                               uz * (G2 * x + G4 * y + G5 * z));
+            // vector fields: the sum over the components, in component order
+            if (dk && qok) {
+              if (comp == 0)
+                dk[(long)q * nc + cell] = dkv;
+              else
+                dk[(long)q * nc + cell] += dkv;
+            }
+          } else {
+            x = acc[(i0) / 4][(i0) % 4];
+            y = acc[(i0 + 1) / 4][(i0 + 1) % 4];
+            z = acc[(i0 + 2) / 4][(i0 + 2) % 4];
+            if constexpr (C == 4) val = acc[(i0 + 3) / 4][(i0 + 3) % 4];
+          }
+          acc[(i0) / 4][(i0) % 4] = s * (G0 * x + G1 * y + G2 * z);
+          acc[(i0 + 1) / 4][(i0 + 1) % 4] = s * (G1 * x + G3 * y + G4 * z);
+          acc[(i0 + 2) / 4][(i0 + 2) % 4] = s * (G2 * x + G4 * y + G5 * z);
+          if constexpr (C == 4) acc[(i0 + 3) / 4][(i0 + 3) % 4] = qok ? sigma * w * adet * val : T(0);
         }
-      } else {
+        if (write_out) {
+          acc_t v;
+          T vv[TL::NVA > 0 ? TL::NVA : 1];
+          TL::integrate(s_eng, acc, g, c16, v, vv);
+          if (valid) {
 #pragma unroll
-        for (int k = 0; k < KP; ++k) kq[k] = T(1);
-      }
-      uint16_t pv[4 + TL::NVA];
-      if (write_out) {
-        // row(g, r) = row(g, 0) + row(0, r): lane part and uniform part
-        const uint32_t pof = ((uint32_t)M::row(g, 0) * (uint32_t)ncp + (uint32_t)cell) * 2u;
+            for (int r = 0; r < 4; ++r)
+              if (TL::NMF == 16 || M::row(g, r) < TL::NMF) s_slot[pv[r]] = v[r];
+            if (TL::NVA > 0 && g < TL::NVA) {
+              T mine = vv[0];
 #pragma unroll
-        // rows beyond the cell's DoFs (fewer than 16 at p <= 2) have no slot
-        for (int r = 0; r < 4; ++r)
-          pv[r] = (TL::NMF == 16 || M::row(g, r) < TL::NMF) ? load_at(d.pos + (long)M::row(0, r) * ncp, pof)
-                                                             : uint16_t(0);
-        if (TL::NVA > 0)
-          pv[4] = load_at(d.pos + 16 * (long)ncp,
-                          ((uint32_t)min(g, TL::NVA - 1) * (uint32_t)ncp + (uint32_t)cell) * 2u);
-      }
-      T ub[NB];
-      T gb[BWD ? NB : 1];
-#pragma unroll
-      for (int ks = 0; ks < NB; ++ks) {
-        const int j = TL::bdof(g, ks);
-        const int l = j < NDOF ? s_lidx[j * kBlockCells + cl] : 0;
-        ub[ks] = j < NDOF ? s_u[l] : T(0);
-        if (BWD) gb[BWD ? ks : 0] = j < NDOF ? s_u[d.nbd_max + l] : T(0);
-      }
-      acc_t acc[MT];
-      TL::interpolate(s_eng, ub, g, c16, acc);
-      acc_t accg[BWD ? MT : 1];
-      if (BWD) {
-        T gtmp[NB];
-#pragma unroll
-        for (int ks = 0; ks < NB; ++ks) gtmp[ks] = gb[BWD ? ks : 0];
-        acc_t tmp[MT];
-        TL::interpolate(s_eng, gtmp, g, c16, tmp);
-#pragma unroll
-        for (int t = 0; t < MT; ++t) accg[BWD ? t : 0] = tmp[t];
-      }
-      // point operator D in registers: item s = C k + c at acc[s / 4][s % 4].
-      // Curved cells: the geometry of point k + 1 is requested once point
-      // k - 1 is done (two points' geometry live at a time).
-      const int ccell = valid ? cell : nc - 1;
-      // per-tile copies of the bases, so that the row addresses derived from
-      // them are not hoisted out of the block loop (36 of them at P3)
-      const T* geot = geo;
-      const T* kapt = kappa;
-      if constexpr (CURV) asm volatile("" : "+s"(geot), "+s"(kapt));
-#pragma unroll
-      for (int k = 0; k < KP; ++k) {
-        T Gk[8];
-        if constexpr (CURV) {
-          const int ip = C * (k > 0 ? k - 1 : 0);
-          point_geo<T, NQ, C>(geot, ncp, kapt, nc, k, g, cell, ccell, acc[ip / 4][ip % 4], Gk);
-        } else {
-#pragma unroll
-          for (int c = 0; c < 7; ++c) Gk[c] = Gc[c];
-          Gk[7] = kq[k];
-        }
-        const T G0 = Gk[0], G1 = Gk[1], G2 = Gk[2], G3 = Gk[3], G4 = Gk[4], G5 = Gk[5], adet = Gk[6];
-        const int q = g + 4 * k;
-        const T w = s_qw[q];
-        const bool qok = valid && q < NQ;
-        const T s = qok ? Gk[7] * w : T(0);
-        const int i0 = C * k;
-        T x, y, z, val = T(0);
-        if (BWD) {
-          const T ux = acc[(i0) / 4][(i0) % 4], uy = acc[(i0 + 1) / 4][(i0 + 1) % 4];
-          const T uz = acc[(i0 + 2) / 4][(i0 + 2) % 4];
-          x = accg[BWD ? (i0) / 4 : 0][(i0) % 4];
-          y = accg[BWD ? (i0 + 1) / 4 : 0][(i0 + 1) % 4];
-          z = accg[BWD ? (i0 + 2) / 4 : 0][(i0 + 2) % 4];
-          if constexpr (C == 4) val = accg[BWD ? (i0 + 3) / 4 : 0][(i0 + 3) % 4];
-          // dkappa = w_q grad_ref(u)^T G grad_ref(g)  (G already holds |det J|)
-          const T dkv = w * (ux * (G0 * x + G1 * y + G2 * z) + uy * (G1 * x + G3 * y + G4 * z) +
-                             uz * (G2 * x + G4 * y + G5 * z));
-          if (dk && qok) dk[(long)q * nc + cell] = dkv;
-        } else {
-          x = acc[(i0) / 4][(i0) % 4];
-          y = acc[(i0 + 1) / 4][(i0 + 1) % 4];
-          z = acc[(i0 + 2) / 4][(i0 + 2) % 4];
-          if constexpr (C == 4) val = acc[(i0 + 3) / 4][(i0 + 3) % 4];
-        }
-        acc[(i0) / 4][(i0) % 4] = s * (G0 * x + G1 * y + G2 * z);
-        acc[(i0 + 1) / 4][(i0 + 1) % 4] = s * (G1 * x + G3 * y + G4 * z);
-        acc[(i0 + 2) / 4][(i0 + 2) % 4] = s * (G2 * x + G4 * y + G5 * z);
-        if constexpr (C == 4) acc[(i0 + 3) / 4][(i0 + 3) % 4] = qok ? sigma * w * adet * val : T(0);
-      }
-      if (write_out) {
-        acc_t v;
-        T vv[TL::NVA > 0 ? TL::NVA : 1];
-        TL::integrate(s_eng, acc, g, c16, v, vv);
-        if (valid) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (TL::NMF == 16 || M::row(g, r) < TL::NMF) s_slot[pv[r]] = v[r];
-          if (TL::NVA > 0 && g < TL::NVA) {
-            T mine = vv[0];
-#pragma unroll
-            for (int jj = 1; jj < (TL::NVA > 0 ? TL::NVA : 1); ++jj) mine = (g == jj) ? vv[jj] : mine;
-            s_slot[pv[4]] = mine;
+              for (int jj = 1; jj < (TL::NVA > 0 ? TL::NVA : 1); ++jj) mine = (g == jj) ? vv[jj] : mine;
+              s_slot[pv[4]] = mine;
+            }
           }
         }
       }
+      __syncthreads();
+      if (write_out)
+        cg_reduce<T>(d, s_slot, nbd, npriv, ps, oo, po, oc, static_cast<T*>(d.partials) + (long)comp * d.n_partials);
+    };
+    if constexpr (NCOMP == 1) {
+      comp_pass(0);
+    } else {
+#pragma unroll 1
+      for (int comp = 0; comp < NCOMP; ++comp) comp_pass(comp);
     }
-    __syncthreads();
-    if (write_out) cg_reduce<T>(d, s_slot, nbd, npriv, ps, oo, po, out);
   }
 }
 
@@ -699,16 +725,21 @@ __global__ void __launch_bounds__(kThreads) cg_vec_kernel(CGDev d, const T* __re
     }
     __syncthreads();
     cg_reduce<T>(d, s_slot, d.blk_nbd[b], d.blk_npriv[b], d.blk_priv_start[b], d.blk_other_off[b],
-                 d.blk_ptr_off[b], out);
+                 d.blk_ptr_off[b], out, static_cast<T*>(d.partials));
   }
 }
 
 // Shared DoFs: sum of the per-block partials in block order.  Constrained
 // DoFs: identity rows (apply/backward), 1 (diagonal), 0 (load vector).
+// blockIdx.y: the component of a vector field (partials, u and out offset by
+// one component each).
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) cg_combine(CGDev d, const T* __restrict__ u, T* __restrict__ out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
-  const T* part = static_cast<const T*>(d.partials);
+  const long cofs = (long)blockIdx.y * d.n_dofs;
+  const T* part = static_cast<const T*>(d.partials) + (long)blockIdx.y * d.n_partials;
+  if (u) u += cofs;
+  out += cofs;
   if (i < d.n_shared) {
     const int p0 = d.sh_ptr[i], p1 = d.sh_ptr[i + 1];
     T s = 0;
@@ -724,14 +755,15 @@ __global__ void __launch_bounds__(256) cg_combine(CGDev d, const T* __restrict__
 }
 
 template <typename T, int MODE>
-hipError_t launch_combine(const CGDev& d, const void* src, void* out, hipStream_t s) {
+hipError_t launch_combine(const CGDev& d, const void* src, void* out, hipStream_t s, int ncomp = 1) {
   const int nfix = d.n_shared + (d.n_dofs - d.n_free);
-  if (nfix > 0) hipLaunchKernelGGL((cg_combine<T, MODE>), dim3((nfix + 255) / 256), dim3(256), 0, s, d, (const T*)src,
-                                   (T*)out);
+  if (nfix > 0)
+    hipLaunchKernelGGL((cg_combine<T, MODE>), dim3((nfix + 255) / 256, ncomp), dim3(256), 0, s, d, (const T*)src,
+                       (T*)out);
   return hipGetLastError();
 }
 
-template <typename T, int NDOF, int NQ, int C, int MODE, bool BF, bool CURV>
+template <typename T, int NDOF, int NQ, int C, int MODE, bool BF, bool CURV, int NCOMP>
 hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void* kappa, void* out, void* dk,
                         hipStream_t s, hipEvent_t* ev) {
   using TL = typename EngineSel<T, NDOF, NQ, C, BF>::type;
@@ -739,7 +771,7 @@ hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void
   const size_t lds = (size_t)TL::LDS_BYTES + (size_t)(TL::NPT + kBlockCells * NDOF + ustage) * sizeof(T) +
                      (size_t)NDOF * kBlockCells * sizeof(uint16_t);
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  auto kern = cg_kernel<T, NDOF, NQ, C, MODE, BF, CURV>;
+  auto kern = cg_kernel<T, NDOF, NQ, C, MODE, BF, CURV, NCOMP>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
@@ -750,7 +782,7 @@ hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void
                         (const T*)u, (const T*)g, (const T*)kappa, (T*)out, (T*)dk);
   e = hipGetLastError();
   if (e != hipSuccess || out == nullptr) return e;
-  return launch_combine<T, MODE>(d, MODE == MODE_BACKWARD ? g : u, out, s);
+  return launch_combine<T, MODE>(d, MODE == MODE_BACKWARD ? g : u, out, s, NCOMP);
 }
 
 template <typename T, int NDOF, int NQ, int MODE, bool CURV>
@@ -769,31 +801,46 @@ hipError_t launch_cg_vec(const CGDev& d, const void* kappa, void* out, hipStream
   return launch_combine<T, MODE>(d, nullptr, out, s);
 }
 
-template <typename T, int NDOF, int NQ, bool BF, bool CURV>
+template <typename T, int NDOF, int NQ, bool BF, bool CURV, int NCOMP>
 hipError_t launch_cg_geo(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
                          void* dk, hipStream_t s, hipEvent_t* ev, bool* supported) {
   const bool mass = d.sigma != 0.0;
   switch (mode) {
     case MODE_APPLY:
-      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_APPLY, BF, CURV>(d, u, g, kappa, out, dk, s, ev)
-                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_APPLY, BF, CURV>(d, u, g, kappa, out, dk, s, ev);
+      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_APPLY, BF, CURV, NCOMP>(d, u, g, kappa, out, dk, s, ev)
+                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_APPLY, BF, CURV, NCOMP>(d, u, g, kappa, out, dk, s, ev);
     case MODE_BACKWARD:
       if (BF) {
         *supported = false;
         return hipSuccess;
       }
-      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_BACKWARD, false, CURV>(d, u, g, kappa, out, dk, s, ev)
-                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_BACKWARD, false, CURV>(d, u, g, kappa, out, dk, s, ev);
+      return mass ? launch_cg_mf<T, NDOF, NQ, 4, MODE_BACKWARD, false, CURV, NCOMP>(d, u, g, kappa, out, dk, s, ev)
+                  : launch_cg_mf<T, NDOF, NQ, 3, MODE_BACKWARD, false, CURV, NCOMP>(d, u, g, kappa, out, dk, s, ev);
+    // the diagonal and load vector are per component (tetmf.cpp replicates them)
     case MODE_DIAG: return launch_cg_vec<T, NDOF, NQ, MODE_DIAG, CURV>(d, kappa, out, s, ev);
     default: return launch_cg_vec<T, NDOF, NQ, MODE_LOAD, CURV>(d, kappa, out, s, ev);
   }
 }
 
+template <typename T, int NDOF, int NQ, bool BF, bool CURV>
+hipError_t launch_cg_comp(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
+                          void* dk, hipStream_t s, hipEvent_t* ev, bool* supported) {
+  if (d.ncomp == 3 && (mode == MODE_APPLY || mode == MODE_BACKWARD)) {
+    if constexpr (BF) {
+      *supported = false;
+      return hipSuccess;
+    } else {
+      return launch_cg_geo<T, NDOF, NQ, false, CURV, 3>(d, mode, u, g, kappa, out, dk, s, ev, supported);
+    }
+  }
+  return launch_cg_geo<T, NDOF, NQ, BF, CURV, 1>(d, mode, u, g, kappa, out, dk, s, ev, supported);
+}
+
 template <typename T, int NDOF, int NQ, bool BF>
 hipError_t launch_cg_mode(const CGDev& d, int mode, const void* u, const void* g, const void* kappa, void* out,
                           void* dk, hipStream_t s, hipEvent_t* ev, bool* supported) {
-  return d.curved ? launch_cg_geo<T, NDOF, NQ, BF, true>(d, mode, u, g, kappa, out, dk, s, ev, supported)
-                  : launch_cg_geo<T, NDOF, NQ, BF, false>(d, mode, u, g, kappa, out, dk, s, ev, supported);
+  return d.curved ? launch_cg_comp<T, NDOF, NQ, BF, true>(d, mode, u, g, kappa, out, dk, s, ev, supported)
+                  : launch_cg_comp<T, NDOF, NQ, BF, false>(d, mode, u, g, kappa, out, dk, s, ev, supported);
 }
 
 template <typename T, bool BF>

@@ -362,6 +362,7 @@ struct tetmf_op {
   CGDev cg{};
   DGDev dg{};
   double flops = 0, bytes = 0;
+  int ncomp = 1;                 // components of a vector field (CG), stored one after another
   bool curved = false;
   const double* qjac = nullptr;  // per-point Jacobians during set-up only (user memory)
   const tetmf_mesh* mesh_tag = nullptr;
@@ -373,6 +374,8 @@ struct tetmf_op {
   bool profiling = false;
   std::vector<hipEvent_t> events;  // pairs
   size_t events_used = 0;          // pairs recorded
+
+  int64_t nvec() const { return n_dofs * ncomp; }  // length of the operator's vectors
 
   hipEvent_t* next_events() {
     if (!profiling) return nullptr;
@@ -841,6 +844,7 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
   d.nbd_max = nbd_max;
   d.sigma = op->sigma;
   d.curved = op->curved ? 1 : 0;
+  d.ncomp = op->ncomp;
   d.geo = op->upload_real(op->curved ? point_geometry(op->qjac, perm, op->nq, op->ncp)
                                      : cell_geometry(m, perm, op->ncp));
   d.blk_priv_start = (const int*)op->upload(priv_start);
@@ -855,7 +859,9 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
   d.slot_ptr = (const uint16_t*)op->upload(slot_ptr);
   d.sh_gid = (const int*)op->upload(sh_gid);
   d.sh_ptr = (const int*)op->upload(sh_ptr);
-  d.partials = op->alloc((size_t)std::max<int64_t>(op->n_partials, 1) * op->esize());
+  if (op->n_partials * op->ncomp > INT32_MAX) throw Error(TETMF_ERR_UNSUPPORTED, "too many partial sums");
+  d.n_partials = (int)op->n_partials;
+  d.partials = op->alloc((size_t)std::max<int64_t>(op->n_partials * op->ncomp, 1) * op->esize());
 }
 
 void setup_dg(tetmf_op* op, const tetmf_mesh& m, bool device) {
@@ -1004,10 +1010,11 @@ void work_model(tetmf_op* op, const tetmf_mesh& m) {
   const double cq = mass ? 37 : 34;
   const double fcell = 4 * r * nq * nd + cq * nq + nd;
   if (op->kind == TETMF_CG) {
-    op->flops = fcell * m.nc;
-    // geometry per cell, or per rule point for curved cells
+    // geometry per cell, or per rule point for curved cells; a vector field
+    // reads the cell data once and its components' vectors each once
     const double ng = (mass ? 7 : 6) * (op->curved ? nq : 1.0);
-    op->bytes = m.nc * (ng * s + 4 * nd + s * nq) + 2 * s * op->n_dofs;
+    op->flops = fcell * m.nc * op->ncomp;
+    op->bytes = m.nc * (ng * s + 4 * nd + s * nq) + 2 * s * (double)op->nvec();
   } else {
     const double nqf = op->nqf;
     const double nbf = (double)(m.nf - m.nif);
@@ -1072,6 +1079,13 @@ int init_op(const tetmf_mesh* mesh, const tetmf_op_desc* d, tetmf_op* op, const 
     const double* x = &d->q_points[3 * q];
     if (!(x[0] >= 0 && x[1] >= 0 && x[2] >= 0 && x[0] + x[1] + x[2] <= 1) || !(d->q_weights[q] > 0))
       return fail(TETMF_ERR_INVALID_ARGUMENT, w + ": quadrature point outside the reference cell");
+  }
+  if (d->n_components != 0 && d->n_components != 1 && d->n_components != 3)
+    return fail(TETMF_ERR_UNSUPPORTED, w + ": n_components must be 1 or 3");
+  if (d->n_components == 3) {
+    if (op->kind != TETMF_CG || op->prec == TETMF_BF16IN)
+      return fail(TETMF_ERR_UNSUPPORTED, w + ": vector fields are supported for CG in FP64 and FP32 only");
+    op->ncomp = 3;
   }
   if (d->q_jacobians) {
     if (op->kind != TETMF_CG) return fail(TETMF_ERR_UNSUPPORTED, w + ": curved cells are supported for CG only");
@@ -1161,6 +1175,7 @@ extern "C" int tetmf_op_info(const tetmf_op* op, tetmf_info* info) {
   if (!op || !info) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_op_info: NULL argument");
   std::memset(info, 0, sizeof(*info));
   info->n_dofs = op->n_dofs;
+  info->n_components = op->ncomp;
   info->n_free = op->n_free;
   info->n_cell = op->nc;
   info->n_face = op->nf;
@@ -1210,6 +1225,17 @@ int run_cg(tetmf_op* op, int mode, const void* u, const void* g, const void* kap
   if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no kernel instantiation for this operator");
   check_hip(e, "kernel launch");
   return TETMF_OK;
+}
+
+// Operator diagonal; every component of a vector field has the scalar
+// operator's diagonal.
+int run_diag(tetmf_op* op, const void* kappa, void* d, void* stream) {
+  int st = run_cg(op, MODE_DIAG, nullptr, nullptr, kappa, d, nullptr, stream);
+  for (int c = 1; c < op->ncomp && st == TETMF_OK; ++c)
+    check_hip(hipMemcpyAsync((char*)d + (size_t)c * op->n_dofs * op->esize(), d, (size_t)op->n_dofs * op->esize(),
+                             hipMemcpyDeviceToDevice, (hipStream_t)stream),
+              "hipMemcpyAsync");
+  return st;
 }
 
 }  // namespace
@@ -1286,7 +1312,7 @@ extern "C" int tetmf_diagonal(tetmf_op* op, const void* kappa_cell, const void* 
   return guarded([&]() -> int {
     if (!op || !d) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_diagonal: NULL argument");
     if (op->kind != TETMF_CG || kappa_face) return fail(TETMF_ERR_UNSUPPORTED, "tetmf_diagonal: only CG operators");
-    return run_cg(op, MODE_DIAG, nullptr, nullptr, kappa_cell, d, nullptr, stream);
+    return run_diag(op, kappa_cell, d, stream);
   });
 }
 
@@ -1294,6 +1320,7 @@ extern "C" int tetmf_load_vector(tetmf_op* op, const void* f, void* b, void* str
   return guarded([&]() -> int {
     if (!op || !b) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_load_vector: NULL argument");
     if (op->kind != TETMF_CG) return fail(TETMF_ERR_UNSUPPORTED, "tetmf_load_vector: only CG operators");
+    if (op->ncomp != 1) return fail(TETMF_ERR_UNSUPPORTED, "tetmf_load_vector: scalar fields only");
     return run_cg(op, MODE_LOAD, nullptr, nullptr, f, b, nullptr, stream);
   });
 }
@@ -1326,7 +1353,7 @@ constexpr int kCheckEvery = 4;
 int pcg(tetmf_op* op, const void* kappa, const void* rhs, void* xsol, void* r, void* z, void* pv, void* q,
         const void* dinv, double* scal, double* part, double rtol_abs2, int max_it, hipStream_t s) {
   const int kp = kernel_prec(op);
-  const int64_t n = op->n_dofs;
+  const int64_t n = op->nvec();
   double* rz = scal + 0;  // rz[0], rz[1]: double buffer
   double* rr = scal + 2;
   check_hip(pcg_init(kp, rhs, dinv, xsol, r, z, pv, part, rz, rr, n, s), "pcg init");
@@ -1352,13 +1379,14 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
     if (op64->kind != TETMF_CG || op64->prec != TETMF_F64)
       return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_solve: op64 must be a CG FP64 operator");
     if (opi && (opi->kind != TETMF_CG || opi->n_dofs != op64->n_dofs || opi->mesh_nc != op64->mesh_nc ||
-                opi->cell_perm != op64->cell_perm || opi->n_free != op64->n_free || opi->curved != op64->curved))
+                opi->cell_perm != op64->cell_perm || opi->n_free != op64->n_free || opi->curved != op64->curved ||
+                opi->ncomp != op64->ncomp))
       return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_solve: inner operator does not match op64");
     if ((const void*)b == (const void*)x) return fail(TETMF_ERR_ALIAS, "tetmf_solve: b and x alias");
     DeviceScope dsc(op64->device);
     hipStream_t s = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
-    const int64_t n = op64->n_dofs;
+    const int64_t n = op64->nvec();
     // scratch: FP64 residual + FP64 correction workspace + inner vectors
     tetmf_op* ow = opi ? opi : op64;
     if (op64->solve_bufs.empty()) {
@@ -1387,7 +1415,7 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
     const int kpi = kernel_prec(ow);
     // Jacobi preconditioner of the inner operator
     if (opts->precond == 1) {
-      int st = run_cg(ow, MODE_DIAG, nullptr, nullptr, opi ? kappai : kappa64, idinv, nullptr, s);
+      int st = run_diag(ow, opi ? kappai : kappa64, idinv, s);
       if (st) return st;
       check_hip(vec_recip(kpi, idinv, n, s), "recip");
     } else {
@@ -1455,7 +1483,7 @@ extern "C" int tetmf_chebyshev(tetmf_op* op, const void* kappa, const void* inv_
     if (x == b || x == inv_diag) return fail(TETMF_ERR_ALIAS, "tetmf_chebyshev: x aliases b or inv_diag");
     DeviceScope dsc(op->device);
     hipStream_t s = (hipStream_t)stream;
-    const int64_t n = op->n_dofs;
+    const int64_t n = op->nvec();
     if (op->cheb_bufs.empty()) {
       for (int i = 0; i < 2; ++i) {
         void* p = nullptr;
@@ -1533,7 +1561,7 @@ extern "C" int tetmf_estimate_lambda_max(tetmf_op* op, const void* kappa, const 
       return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_estimate_lambda_max: n_iter must be in 1..500");
     DeviceScope dsc(op->device);
     hipStream_t s = (hipStream_t)stream;
-    const int64_t n = op->n_dofs;
+    const int64_t n = op->nvec();
     const size_t vb = std::max<size_t>((size_t)n * op->esize(), 16);
     // temporaries, freed on every exit path
     struct Tmp {

@@ -144,3 +144,21 @@ def test_curved_setup_checks():
     assert e.value.status == -4
     with pytest.raises(ValueError):
         tm.check_setup(mesh, 2, (qp, qw), q_jacobians=jac[:, :3])
+
+
+def test_vector_setup_checks():
+    """Vector fields: allowed component counts and kinds (host only)."""
+    import paper_2509_10226_amd as tm
+    xyz, tets = synth.kuhn_cube_mesh(2, 0.1, 0)
+    qp, qw = synth.tet_rule(4)
+    mesh = tm.Mesh(xyz, tets)
+    assert tm.check_setup(mesh, 2, (qp, qw), n_components=3) == tm.check_setup(mesh, 2, (qp, qw))
+    for bad in (2, 4, -1):
+        with pytest.raises(tm.TetmfError) as e:
+            tm.check_setup(mesh, 2, (qp, qw), n_components=bad)
+        assert e.value.status == -4
+    with pytest.raises(tm.TetmfError):
+        tm.check_setup(mesh, 2, (qp, qw), precision="bf16in", n_components=3)
+    fp, fw = synth.tri_rule(4)
+    with pytest.raises(tm.TetmfError):
+        tm.check_setup(mesh, 2, (qp, qw), kind="dg", frule=(fp, fw), n_components=3)
