@@ -37,6 +37,7 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16in": 2500.0}   # MI355X dense mat
 PEAK_HBM_GBS = 8000.0
 METRIC = "DoFs/s per operator apply, p=3 CG, FP64 vs FP32-MFMA; % of roofline"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_apply_p3_n64_traffic.txt")
+TRAFFIC_FILE_CURVED = os.path.join(ROOT, "profiles", "cg_curved_p3_n64_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2509_10226_amd", "csrc", "kernels.hip")
 
 
@@ -45,12 +46,12 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(prec):
+def read_traffic(prec, path=TRAFFIC_FILE):
     """Calibrated HBM bytes per launch from the committed counter summary, or None."""
-    if not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.lstrip().startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
@@ -94,7 +95,8 @@ def roofline(op, prec, avg_ms, traffic_key=None):
     flops = op.info["flops_per_apply"]
     bytes_alg = op.info["bytes_per_apply"]
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    traffic = read_traffic(prec) if traffic_key is None else None
+    traffic = {None: lambda: read_traffic(prec), "curved": lambda: read_traffic(prec, TRAFFIC_FILE_CURVED)}.get(
+        traffic_key, lambda: None)()
     gbs = bytes_alg / (avg_ms * 1e-3) / 1e9
     ridge = PEAK_TFLOPS[prec] * 1e12 / (PEAK_HBM_GBS * 1e9)
     if flops / bytes_alg < ridge:

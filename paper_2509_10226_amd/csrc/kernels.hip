@@ -1283,22 +1283,51 @@ hipError_t launch_dg(const DGDev& d, int prec, int ndof, int nq, int nqf, const 
 // ---------------------------------------------------------------------------
 // layout of per-point cell data: user [n_cell][nq] FP64 <-> library [nq][n_cell]
 
+// Per-point cell data between the user layout [n_cell][nq] (FP64, user cell
+// order) and the library layout [nq][n_cell] (op precision, library order):
+// a transpose with a gather/scatter over cells, staged through LDS so that
+// both sides are read and written in whole rows (64 cells per workgroup;
+// every user row of nq values is contiguous).
+constexpr int kLayoutCells = 64;
+constexpr int kLayoutMaxQ = 64;
+
 template <typename T>
-__global__ void layout_kernel(int to_user, const int* __restrict__ perm, int nc, int nq, const void* src, void* dst) {
-  const long i = (long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (long)nc * nq) return;
-  const int q = (int)(i / nc), c = (int)(i % nc);
-  const long user = (long)perm[c] * nq + q;
-  if (!to_user)
-    static_cast<T*>(dst)[i] = (T) static_cast<const double*>(src)[user];
-  else
-    static_cast<double*>(dst)[user] = (double)static_cast<const T*>(src)[i];
+__global__ void __launch_bounds__(256) layout_kernel(int to_user, const int* __restrict__ perm, int nc, int nq,
+                                                     const void* src, void* dst) {
+  __shared__ double s[kLayoutCells * (kLayoutMaxQ + 1)];
+  const int c0 = blockIdx.x * kLayoutCells;
+  const int ncb = min(kLayoutCells, nc - c0);
+  const int ld = nq + 1;  // odd row stride: the column reads hit distinct banks
+  const int n = ncb * nq;
+  if (!to_user) {
+    // user rows (coalesced within each row) -> LDS [cell][q]
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const int cl = i / nq, q = i % nq;
+      s[cl * ld + q] = static_cast<const double*>(src)[(long)perm[c0 + cl] * nq + q];
+    }
+    __syncthreads();
+    // LDS -> library rows [q][c0 .. c0 + ncb)
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const int q = i / ncb, cl = i % ncb;
+      static_cast<T*>(dst)[(long)q * nc + c0 + cl] = (T)s[cl * ld + q];
+    }
+  } else {
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const int q = i / ncb, cl = i % ncb;
+      s[cl * ld + q] = (double)static_cast<const T*>(src)[(long)q * nc + c0 + cl];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const int cl = i / nq, q = i % nq;
+      static_cast<double*>(dst)[(long)perm[c0 + cl] * nq + q] = s[cl * ld + q];
+    }
+  }
 }
 
 hipError_t launch_layout(int prec, int to_user, const int* cell_perm, int n_cell, int nq, const void* src, void* dst,
                          hipStream_t s) {
-  const long n = (long)n_cell * nq;
-  const int grid = (int)((n + 255) / 256);
+  if (nq < 1 || nq > kLayoutMaxQ || n_cell < 1) return hipErrorInvalidValue;
+  const int grid = (n_cell + kLayoutCells - 1) / kLayoutCells;
   if (prec == PREC_F64)
     hipLaunchKernelGGL(layout_kernel<double>, dim3(grid), dim3(256), 0, s, to_user, cell_perm, n_cell, nq, src, dst);
   else
