@@ -715,18 +715,25 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
     }
   }
   // --- final numbering: per block, private DoFs (contiguous), then newly
-  // touched shared free DoFs; constrained DoFs last.
+  // touched shared free DoFs; constrained DoFs last.  Private DoFs are
+  // ordered by the number of the block's cells that hold them (most first):
+  // the kernels sum each DoF's slots in one lane, and a wave takes as many
+  // steps as its longest sum, so DoFs with similar counts share a wave.
   std::vector<int64_t> gid(ntmp, -1);
   std::vector<int32_t> priv_start(nb), npriv(nb);
+  std::vector<int32_t> mult(ntmp, 0);
   int64_t next = 0;
   for (int64_t b = 0; b < nb; ++b) {
     int64_t c0 = b * kBlockCells, c1 = std::min(nc, c0 + kBlockCells);
     priv_start[b] = (int32_t)next;
+    std::vector<int64_t> cand;
     for (int64_t i = c0; i < c1; ++i)
       for (int j = 0; j < nd; ++j) {
         int64_t t = tmp[(size_t)i * nd + j];
-        if (gid[t] < 0 && !cons[t] && bmin[t] == bmax[t]) gid[t] = next++;
+        if (!cons[t] && bmin[t] == bmax[t] && mult[t]++ == 0) cand.push_back(t);
       }
+    std::stable_sort(cand.begin(), cand.end(), [&](int64_t a, int64_t c) { return mult[a] > mult[c]; });
+    for (int64_t t : cand) gid[t] = next++;
     npriv[b] = (int32_t)(next - priv_start[b]);
     for (int64_t i = c0; i < c1; ++i)
       for (int j = 0; j < nd; ++j) {
@@ -771,7 +778,7 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
   std::vector<int32_t> other_gid, other_pslot;
   std::vector<uint16_t> slot_ptr;
   std::vector<uint16_t> lidx((size_t)nd * op->ncp, 0), pos((size_t)nd * op->ncp, 0);
-  std::vector<int32_t> stamp(op->n_dofs, -1), local_of(op->n_dofs, 0);
+  std::vector<int32_t> stamp(op->n_dofs, -1), local_of(op->n_dofs, 0), occ(op->n_dofs, 0);
   std::vector<int32_t> sh_count(sh_gid.size(), 0);
   std::vector<std::vector<int32_t>> block_shared(nb);
   int nbd_max = 0;
@@ -782,15 +789,22 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
     for (int64_t i = c0; i < c1; ++i)
       for (int j = 0; j < nd; ++j) {
         int64_t g = gid[tmp[(size_t)i * nd + j]];
-        if (stamp[g] == b) continue;
+        if (stamp[g] == b) {
+          if (local_of[g] < 0) occ[g]++;
+          continue;
+        }
         stamp[g] = (int32_t)b;
         if (g >= priv_start[b] && g < priv_start[b] + npriv[b]) {
           local_of[g] = (int32_t)(g - priv_start[b]);
         } else {
-          local_of[g] = nloc++;
+          local_of[g] = -1;
+          occ[g] = 1;
           others.push_back((int32_t)g);
         }
       }
+    // the block's other DoFs, likewise ordered by their number of slots here
+    std::stable_sort(others.begin(), others.end(), [&](int32_t a, int32_t c) { return occ[a] > occ[c]; });
+    for (int32_t g : others) local_of[g] = nloc++;
     blk_nbd[b] = nloc;
     nbd_max = std::max(nbd_max, nloc);
     if (nloc > kBlockCells * nd) throw Error(TETMF_ERR_DEVICE, "internal: block DoF count overflow");
