@@ -391,8 +391,14 @@ __device__ inline void cg_reduce(const CGDev& d, const T* __restrict__ s_slot, i
 #pragma unroll
     for (int i = 0; i < kStageUnroll; ++i) {
       const int k = k0 + i * kThreads + threadIdx.x;
+      // two slots per step (same left-to-right order of the sum)
       T s = 0;
-      for (int p = p0[i]; p < p1[i]; ++p) s += s_slot[p];
+      int p = p0[i];
+      for (; p + 1 < p1[i]; p += 2) {
+        s += s_slot[p];
+        s += s_slot[p + 1];
+      }
+      if (p < p1[i]) s += s_slot[p];
       if (dst[i] == -2)
         out[ps + k] = s;
       else if (dst[i] >= 0)
@@ -475,7 +481,8 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
           for (int i = 0; i < (W + kThreads - 1) / kThreads; ++i) {
             const int w = i * kThreads + st;
             const int j = (2 * w) / kBlockCells, cl = (2 * w) % kBlockCells;
-            wv[i] = w < W ? src[((long)j * ncp + (long)b * kBlockCells + cl) / 2] : 0u;
+            // word (j ncp + b kBlockCells + cl) / 2: block base + 32-bit byte offset
+            wv[i] = w < W ? load_at(src + (long)b * (kBlockCells / 2), (uint32_t)(2 * (j * ncp + cl))) : 0u;
           }
         }
         // DoF values: all index loads first, then all value loads (clamped
@@ -489,16 +496,16 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
           for (int i = 0; i < kStageUnroll; ++i) {
             const int k = k0 + i * kThreads + st;
             const int oi = min(max(k - npriv, 0), max(nother - 1, 0));
-            const int og = d.other_gid[oo + oi];
+            const int og = load_at(d.other_gid + oo, (uint32_t)oi * 4u);
             gi[i] = (k < npriv) ? ps + k : og;
             ok[i] = k < nbd && (k < npriv || og < d.n_free);
           }
           T uv[kStageUnroll], gv[kStageUnroll];
 #pragma unroll
           for (int i = 0; i < kStageUnroll; ++i) {
-            const int src_i = ok[i] ? gi[i] : 0;
-            uv[i] = uc[src_i];
-            if (BWD) gv[i] = gc[src_i];
+            const uint32_t src_o = (uint32_t)(ok[i] ? gi[i] : 0) * (uint32_t)sizeof(T);
+            uv[i] = load_at(uc, src_o);
+            if (BWD) gv[i] = load_at(gc, src_o);
             uv[i] = ok[i] ? uv[i] : T(0);
             if (BWD) gv[i] = ok[i] ? gv[i] : T(0);
           }
