@@ -136,6 +136,25 @@ def cpu_baseline(n_sample=20):
     t2 = time.perf_counter()
     t_spmv = (t2 - t1) / reps
     nd = A.shape[0]
+    # the GPU operator in each precision on the same sample, against the
+    # oracle's product (DoFs matched by coordinates)
+    parity = {}
+    try:
+        import torch
+        from scipy.spatial import cKDTree
+
+        import paper_2509_10226_amd as tm
+        mesh = tm.Mesh(xyz, tets)
+        for prec in ("f64", "f32", "bf16in"):
+            op = tm.Operator(mesh, 3, (qp, qw), precision=prec)
+            _, dxyz, _ = op.numbering()
+            idx = cKDTree(d["xyz"]).query(dxyz)[1]
+            kl = op.cell_data_to_library(torch.from_numpy(kap).cuda())
+            v = op.apply(torch.from_numpy(u[idx]).cuda().to(op.dtype), kl).double().cpu().numpy()
+            parity[prec] = float(np.linalg.norm(v - y[idx]) / np.linalg.norm(y))
+            del op
+    except RuntimeError as e:  # no GPU: the oracle timing stands alone
+        parity = {"error": str(e)}
     return {
         "value": round(nd / ((t1 - t0) + t_spmv), 1),
         "unit": "DoFs/s",
@@ -147,6 +166,7 @@ def cpu_baseline(n_sample=20):
         "spmv_only_value": round(nd / t_spmv, 1),
         "assembly_s": round(t1 - t0, 3),
         "checksum": float(np.abs(y).sum()),
+        "gpu_rel_err_vs_oracle": parity,
     }
 
 
@@ -480,7 +500,7 @@ def main():
     xyz, tets, qp, qw, kap = build_workload(args.n)
     t_setup = time.perf_counter()
     mesh = tm.Mesh(xyz, tets)
-    results = {}
+    results, outs = {}, {}
     for prec in args.precisions.split(","):
         op = tm.Operator(mesh, 3, (qp, qw), precision=prec)
         setup_s = time.perf_counter() - t_setup
@@ -488,6 +508,7 @@ def main():
         g = torch.Generator(device="cpu").manual_seed(2)
         u = (torch.rand(op.n_dofs, generator=g, dtype=torch.float64) * 2 - 1).to(dev, op.dtype)
         ms_step, ms_kernel, out = time_gpu(op, kl, u, args.steps, args.warmup)
+        outs[prec] = out.double()
         results[prec] = {
             "value": op.n_dofs / (ms_step * 1e-3),
             "ms_per_step": ms_step,
@@ -531,6 +552,12 @@ def main():
         if prec != main_prec:
             line[prec] = {"value": round(rr["value"], 1), "ms_per_step": round(rr["ms_per_step"], 5),
                           "roofline": rr["roofline"]}
+            if "f64" in outs:
+                # same input (rounded to the operand precision); the FP64
+                # operator matches the oracle to 1e-12 (tests)
+                ref = outs["f64"]
+                line[prec]["rel_diff_vs_f64_operator"] = float(torch.linalg.norm(outs[prec] - ref) /
+                                                               torch.linalg.norm(ref))
     line["setup_s"] = r["setup_s"]
     line["blocks"] = {"n_blocks": r["blocks"], "shared_dofs": r["shared_dofs"], "partials": r["partials"]}
     if not args.no_cpu_baseline and args.n == 64:
