@@ -70,21 +70,68 @@ def build_workload(n, seed=0):
 
 
 def time_gpu(op, kl, u, steps, warmup):
+    """(ms per apply, ms per cell-kernel launch, output).  The apply time is
+    taken over `steps` launches with profiling off; the kernel time over a
+    second `steps` launches with the HIP event pair on (the events add host
+    work and dispatch latency to every call, so they are kept out of the
+    first loop)."""
     import torch
     out = torch.empty_like(u)
     for _ in range(warmup):
         op.apply(u, kl, out=out)
     torch.cuda.synchronize()
-    op.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         op.apply(u, kl, out=out)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    op.profile(True)
+    for _ in range(steps):
+        op.apply(u, kl, out=out)
+    torch.cuda.synchronize()
     op.profile(False)
     ms_kernel, launches = op.profile_read()
     assert launches == steps
-    return (t1 - t0) * 1e3 / steps, ms_kernel / launches, out
+    return ms_step, ms_kernel / launches, out
+
+
+def time_graph(op, kl, u, steps, warmup, ref):
+    """ms per apply when one apply (cell kernel + combine) is captured in a
+    HIP graph and replayed; None unless every checked replay equals the
+    eager result `ref` bitwise (with eager work between the replays)."""
+    import torch
+    try:
+        out = torch.empty_like(u)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                op.apply(u, kl, out=out)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            op.apply(u, kl, out=out)
+        for _ in range(3):
+            out.zero_()
+            graph.replay()
+            torch.cuda.synchronize()
+            if not torch.equal(out, ref):
+                return None
+            op.apply(u, kl)
+            torch.cuda.synchronize()
+        for _ in range(warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        del graph
+        return ms
+    except RuntimeError:
+        return None
 
 
 def roofline(op, prec, avg_ms, traffic_key=None):
@@ -183,20 +230,23 @@ def copy_calibration(mib=1024, reps=3):
 
 
 def _time_call(fn, steps, warmup, op=None):
-    """Milliseconds per call over `steps` timed calls after `warmup` calls;
-    with op, its kernel profiling covers exactly the timed calls."""
+    """Milliseconds per call over `steps` timed calls after `warmup` calls,
+    profiling off; with op, a second loop of `steps` calls with its kernel
+    profiling on follows (read with op.profile_read())."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    if op is not None:
-        op.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     if op is not None:
+        op.profile(True)
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
         op.profile(False)
     return ms
 
@@ -507,11 +557,15 @@ def main():
         kl = op.cell_data_to_library(torch.from_numpy(kap).to(dev))
         g = torch.Generator(device="cpu").manual_seed(2)
         u = (torch.rand(op.n_dofs, generator=g, dtype=torch.float64) * 2 - 1).to(dev, op.dtype)
-        ms_step, ms_kernel, out = time_gpu(op, kl, u, args.steps, args.warmup)
+        ms_eager, ms_kernel, out = time_gpu(op, kl, u, args.steps, args.warmup)
+        ms_graph = time_graph(op, kl, u, args.steps, args.warmup, out)
+        ms_step = ms_graph if ms_graph is not None else ms_eager
         outs[prec] = out.double()
         results[prec] = {
             "value": op.n_dofs / (ms_step * 1e-3),
             "ms_per_step": ms_step,
+            "ms_per_step_eager": ms_eager,
+            "timing": "graph" if ms_graph is not None else "eager",
             "roofline": roofline(op, prec, ms_kernel),
             "n_dofs": op.n_dofs,
             "n_cell": op.n_cell,
@@ -532,6 +586,10 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(r["ms_per_step"], 5),
+        "ms_per_step_eager": round(r["ms_per_step_eager"], 5),
+        "timing": (("one apply (cell kernel + combine) captured in a HIP graph and replayed; replays checked "
+                    "bitwise against the eager result; ms_per_step_eager: the same calls launched one by one")
+                   if r["timing"] == "graph" else "applies launched one by one"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -551,6 +609,7 @@ def main():
     for prec, rr in results.items():
         if prec != main_prec:
             line[prec] = {"value": round(rr["value"], 1), "ms_per_step": round(rr["ms_per_step"], 5),
+                          "ms_per_step_eager": round(rr["ms_per_step_eager"], 5), "timing": rr["timing"],
                           "roofline": rr["roofline"]}
             if "f64" in outs:
                 # same input (rounded to the operand precision); the FP64
