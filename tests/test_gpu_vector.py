@@ -115,3 +115,30 @@ def test_vector_load_vector_unsupported():
     c = setup_vec(2, 1, 2)
     with pytest.raises(tm.TetmfError):
         c["op"].load_vector()
+
+
+def test_vector_solve_rejects_mismatched_inner_operator():
+    import paper_2509_10226_amd as tm
+    xyz, tets = synth.kuhn_cube_mesh(3, 0.15, 0)
+    qp, qw = synth.tet_rule(4)
+    mesh = tm.Mesh(xyz, tets)
+    opv = tm.Operator(mesh, 2, (qp, qw), bc="dirichlet", n_components=3)
+    ops32 = tm.Operator(mesh, 2, (qp, qw), bc="dirichlet", precision="f32")
+    b = torch.zeros(opv.n_vec, dtype=torch.float64, device="cuda")
+    with pytest.raises(tm.TetmfError) as e:
+        opv.solve(b, inner=ops32)
+    assert e.value.status == -1
+
+
+def test_vector_autograd():
+    """torch.autograd through apply_autograd on a vector field returns the
+    kernel gradients (the kappa gradient summed over the components)."""
+    import paper_2509_10226_amd as tm
+    c = setup_vec(3, 2, 4)
+    n = c["op"].n_vec
+    ut = torch.from_numpy(synth.uniform(6, synth.STREAM_U, n)).cuda().requires_grad_()
+    gt = torch.from_numpy(synth.uniform(6, synth.STREAM_F, n)).cuda()
+    kc = c["kl"].clone().requires_grad_()
+    (tm.apply_autograd(c["op"], ut, kc) * gt).sum().backward()
+    du, dk = c["op"].backward(ut.detach(), gt, c["kl"])
+    assert torch.equal(ut.grad, du) and torch.equal(kc.grad, dk)
