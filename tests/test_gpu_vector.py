@@ -142,3 +142,34 @@ def test_vector_autograd():
     (tm.apply_autograd(c["op"], ut, kc) * gt).sum().backward()
     du, dk = c["op"].backward(ut.detach(), gt, c["kl"])
     assert torch.equal(ut.grad, du) and torch.equal(kc.grad, dk)
+
+
+@pytest.mark.parametrize("curved", [False, True])
+def test_vector_equals_scalar_per_component(curved):
+    """Each component of the vector apply and of the Chebyshev smoother (no
+    inner products) is bitwise the scalar operator's result on that
+    component: the same kernel arithmetic runs per component."""
+    import paper_2509_10226_amd as tm
+    xyz, tets = synth.kuhn_cube_mesh(5, 0.15, 0)
+    qp, qw = synth.tet_rule(6)
+    jac = synth.curved_jacobians(xyz, tets, qp, 0.25) if curved else None
+    mesh = tm.Mesh(xyz, tets)
+    opv = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet", sigma=0.5, q_jacobians=jac, n_components=3)
+    ops = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet", sigma=0.5, q_jacobians=jac)
+    kap = synth.lognormal(0, synth.STREAM_KAPPA_CELL, (tets.shape[0], qw.size), sigma=0.5)
+    kl = ops.cell_data_to_library(torch.from_numpy(kap).cuda())
+    n = ops.n_dofs
+    u = torch.from_numpy(synth.uniform(7, synth.STREAM_U, 3 * n)).cuda()
+    v = opv.apply(u, kl)
+    for c in range(3):
+        assert torch.equal(v[c * n:(c + 1) * n], ops.apply(u[c * n:(c + 1) * n].contiguous(), kl))
+    dv, ds = opv.diagonal(kl), ops.diagonal(kl)
+    assert all(torch.equal(dv[c * n:(c + 1) * n], ds) for c in range(3))
+    inv = 1.0 / dv
+    lam_v = opv.estimate_lambda_max(inv, kappa=kl)
+    lam_s = ops.estimate_lambda_max(1.0 / ds, kappa=kl)
+    assert abs(lam_v - lam_s) <= 0.05 * lam_s
+    xv = opv.chebyshev(u, inv, 4, lam_s / 15, 1.1 * lam_s, kappa=kl)
+    for c in range(3):
+        xs = ops.chebyshev(u[c * n:(c + 1) * n].contiguous(), 1.0 / ds, 4, lam_s / 15, 1.1 * lam_s, kappa=kl)
+        assert torch.equal(xv[c * n:(c + 1) * n], xs)
