@@ -748,9 +748,18 @@ __global__ void __launch_bounds__(256) cg_combine(CGDev d, const T* __restrict__
   if (u) u += cofs;
   out += cofs;
   if (i < d.n_shared) {
+    // at least two partial sums per shared DoF (checked at set-up); the
+    // first four are loaded together, the sum keeps block order
     const int p0 = d.sh_ptr[i], p1 = d.sh_ptr[i + 1];
+    const T a0 = part[p0], a1 = part[p0 + 1];
+    const T a2 = p0 + 2 < p1 ? part[p0 + 2] : T(0);
+    const T a3 = p0 + 3 < p1 ? part[p0 + 3] : T(0);
     T s = 0;
-    for (int p = p0; p < p1; ++p) s += part[p];
+    s += a0;
+    s += a1;
+    if (p0 + 2 < p1) s += a2;
+    if (p0 + 3 < p1) s += a3;
+    for (int p = p0 + 4; p < p1; ++p) s += part[p];
     out[d.sh_gid[i]] = s;
   } else {
     const int c = i - d.n_shared;

@@ -588,8 +588,9 @@ std::string validate_cg(const tetmf_op* op, int nd, const std::vector<int32_t>& 
   if ((int64_t)lidx.size() != nd * ncp || (int64_t)pos.size() != nd * ncp) return bad("lidx/pos size");
   if (other_gid.empty() || other_gid.size() != other_pslot.size()) return bad("other lists");
   if (sh_ptr.size() != sh_gid.size() + 1 || sh_ptr.back() != op->n_partials) return bad("shared CSR");
+  // every shared DoF has at least two partial sums (cg_combine reads two unconditionally)
   for (size_t s = 0; s + 1 < sh_ptr.size(); ++s)
-    if (sh_ptr[s] > sh_ptr[s + 1] || sh_gid[s] < 0 || sh_gid[s] >= op->n_free) return bad("shared entry");
+    if (sh_ptr[s] + 2 > sh_ptr[s + 1] || sh_gid[s] < 0 || sh_gid[s] >= op->n_free) return bad("shared entry");
   std::vector<int64_t> pslot_seen(op->n_partials, 0);
   std::vector<int64_t> owner(op->n_dofs, 0);
   for (int64_t b = 0; b < nb; ++b) {
