@@ -152,8 +152,16 @@ struct Tile {
   __device__ static inline void interpolate(const T* __restrict__ s_tab, const T (&ub)[KS], int g, int c16,
                                             acc_t (&acc)[MT]) {
     const int gi = M::row_g(c16), ri = M::row_r(c16);
+    // FP64 with a partly used last tile (NS % 4 items of 4, e.g. 2 at P3):
+    // its items run on the 4x4x4 four-block product instead (see integrate
+    // for the lane layout: with block b = cells 4b..4b+3, K = the four
+    // DoFs of a step on the lane groups and rows = the lane groups, the B
+    // operand is ub itself and lane group g receives the item of its own
+    // points), at a quarter of the cost per item of the 16-row product.
+    constexpr bool kSplitLast = sizeof(T) == 8 && NS % 4 != 0;
+    constexpr int MTF = kSplitLast ? MT - 1 : MT;
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
+    for (int t = 0; t < MTF; ++t) {
       const int s = 4 * t + ri;
       const int base = ((gi + 4 * (s / C)) * C + s % C) * NDP;
       acc[t] = acc_t{0, 0, 0, 0};
@@ -162,6 +170,23 @@ struct Tile {
         const int col = 4 * ks + g;
         const T a = (NDOF % 4 == 0 || col < NDOF) ? s_tab[base + col] : T(0);
         acc[t] = M::mma(a, ub[ks], acc[t]);
+      }
+    }
+    if constexpr (kSplitLast) {
+      const int gq = c16 & 3;  // row of A supplied by this lane: the item's lane group
+      acc[MT - 1] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < NS % 4; ++r) {
+        const int s = 4 * (MT - 1) + r;
+        const int base = ((gq + 4 * (s / C)) * C + s % C) * NDP;
+        T d = T(0);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const int col = 4 * ks + g;
+          const T a = (NDOF % 4 == 0 || col < NDOF) ? s_tab[base + col] : T(0);
+          d = __builtin_amdgcn_mfma_f64_4x4x4f64(a, ub[ks], d, 0, 0, 0);
+        }
+        acc[MT - 1][r] = d;
       }
     }
   }
