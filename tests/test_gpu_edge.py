@@ -16,14 +16,18 @@ ONE_TET = (np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.0], [0.2, 1.0, 0.1], [0.1, 0.
            np.array([[0, 1, 2, 3]], dtype=np.int32))
 
 
-def _cg_check(xyz, tets, p, h, bc="neumann", sigma=0.0, precision="f64"):
+def _cg_check(xyz, tets, p, h, bc="neumann", sigma=0.0, precision="f64", curved=False, ncomp=1):
     import paper_2509_10226_amd as tm
     qp, qw = synth.tet_rule(2 * p)
     kap = synth.lognormal(0, synth.STREAM_KAPPA_CELL, (tets.shape[0], qw.size), sigma=0.5)
-    A, d = oracle.assemble_cg(xyz, tets, p, qp, qw, kappa=kap, sigma=sigma, dirichlet=(bc == "dirichlet"))
-    op = tm.Operator(tm.Mesh(xyz, tets), p, (qp, qw), bc=bc, sigma=sigma, precision=precision)
+    jac = synth.curved_jacobians(xyz, tets, qp, 0.25) if curved else None
+    A, d = oracle.assemble_cg(xyz, tets, p, qp, qw, kappa=kap, sigma=sigma, dirichlet=(bc == "dirichlet"), jac=jac)
+    A = oracle.vector_operator(A, ncomp) if ncomp > 1 else A
+    op = tm.Operator(tm.Mesh(xyz, tets), p, (qp, qw), bc=bc, sigma=sigma, precision=precision, q_jacobians=jac,
+                     n_components=ncomp)
     _, dxyz, _ = op.numbering()
     idx = cg_map(dxyz, d["xyz"], h)
+    idx = np.concatenate([c * d["xyz"].shape[0] + idx for c in range(ncomp)])
     kl = op.cell_data_to_library(torch.from_numpy(kap).cuda())
     u = synth.uniform(0, synth.STREAM_U, A.shape[0])
     if precision != "f64":
@@ -77,3 +81,37 @@ def test_dg_small(mesh):
     u = synth.uniform(0, synth.STREAM_U, A.shape[0])
     v = op.apply(torch.from_numpy(u[idx]).cuda(), klc, klf).cpu().numpy()
     assert rel_err(v, (A @ u)[idx]) <= 1e-12
+
+
+@pytest.mark.parametrize("mesh", ["one_tet", "ragged"])
+@pytest.mark.parametrize("curved,ncomp", [(True, 1), (False, 3), (True, 3)])
+def test_cg_curved_and_vector_edge_meshes(mesh, curved, ncomp):
+    if mesh == "one_tet":
+        xyz, tets = ONE_TET
+        h = 1.0
+    else:
+        xyz, tets = synth.kuhn_cube_mesh(7, 0.15, 1)
+        h = 1.0 / 7
+    assert _cg_check(xyz, tets, 3, h, bc="dirichlet", sigma=0.3, curved=curved, ncomp=ncomp) <= 1e-12
+
+
+@pytest.mark.parametrize("mesh", ["one_tet", "one_cube"])
+def test_dg_backward_small(mesh):
+    """SIPG coefficient gradients on meshes with only boundary faces (one
+    tetrahedron) and with both kinds (one cube)."""
+    import paper_2509_10226_amd as tm
+    xyz, tets = ONE_TET if mesh == "one_tet" else synth.kuhn_cube_mesh(1, 0.0, 0)
+    qp, qw = synth.tet_rule(4)
+    fp, fw = synth.tri_rule(4)
+    m = tm.Mesh(xyz, tets)
+    op = tm.Operator(m, 2, (qp, qw), kind="dg", frule=(fp, fw), bc="dirichlet")
+    _, dxyz, dcell = op.numbering()
+    idx = dg_map(dxyz, dcell, xyz, tets, 2)
+    n = op.n_dofs
+    u = synth.uniform(1, synth.STREAM_U, n)
+    g = synth.uniform(1, synth.STREAM_F, n)
+    _, dk, dkf = op.backward(torch.from_numpy(u[idx]).cuda(), torch.from_numpy(g[idx]).cuda(), need_du=False,
+                             need_dkappa_face=True)
+    dkc_o, dkf_o = oracle.dg_kappa_grad(xyz, tets, 2, qp, qw, fp, fw, u, g, bc="dirichlet")
+    assert rel_err(op.cell_data_to_user(dk).cpu().numpy(), dkc_o) <= 1e-12
+    assert rel_err(dkf.cpu().numpy().T, dkf_o) <= 1e-12
