@@ -614,6 +614,10 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
           if (BWD) gb[BWD ? ks : 0] = j < NDOF ? s_u[d.nbd_max + l] : T(0);
         }
         acc_t acc[MT];
+        // matrix-core section of the tile at raised wave priority: the
+        // arbiter then prefers the waves issuing products over those in
+        // their staging, gather or reduction code
+        __builtin_amdgcn_s_setprio(1);
         TL::interpolate(s_eng, ub, g, c16, acc);
         acc_t accg[BWD ? MT : 1];
         if (BWD) {
@@ -696,6 +700,7 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
             }
           }
         }
+        __builtin_amdgcn_s_setprio(0);
       }
       __syncthreads();
       if (write_out)
@@ -991,6 +996,7 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
         kq[k] = kc ? kc[(long)(q < NQ ? q : NQ - 1) * nc + cc] : T(1);
       }
       acc_t acc[TC::MT];
+      __builtin_amdgcn_s_setprio(1);  // matrix-core section at raised wave priority
       TC::interpolate(s_tab, ub, g, c16, acc);
 #pragma unroll
       for (int k = 0; k < TC::KP; ++k) {
@@ -1019,6 +1025,7 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
         for (int jj = 1; jj < (TC::NVA > 0 ? TC::NVA : 1); ++jj) mine = (g == jj) ? vv[jj] : mine;
         so[c16 * NDOF + 16 + g] = mine;
       }
+      __builtin_amdgcn_s_setprio(0);
     }
     // ---- face terms
 #pragma unroll 1
@@ -1056,6 +1063,7 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
         up[s] = (!boundary && j < NDOF) ? bq : T(0);
       }
       acc_t am[TF::MT], ap[TF::MT];
+      __builtin_amdgcn_s_setprio(1);
       TF::interpolate(s_ftab, um, g, c16, am);
       TF::interpolate(s_ftab, up, g, c16, ap);
 #pragma unroll
@@ -1089,6 +1097,7 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
         for (int jj = 1; jj < (TF::NVA > 0 ? TF::NVA : 1); ++jj) mine = (g == jj) ? vvf[jj] : mine;
         so[c16 * NDOF + s_perm[ro * NDOF + 16 + g]] += mine;
       }
+      __builtin_amdgcn_s_setprio(0);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
     // ---- store the tile (contiguous 16 x NDOF block of the DG vector)
