@@ -100,8 +100,8 @@ typedef struct {
    * DEGENERATE_CELL when some |det J_q| <= 1e-12 |J_q|_F^3 or is not finite. */
   const double* q_jacobians;
   /* Components of the field (Sec. 3.2, vector-valued problems without
-   * coupling between the components): 0 or 1 scalar; 3 a vector field, CG in
-   * F64 or F32 only (else UNSUPPORTED).  Every vector of the operator then
+   * coupling between the components): 0 or 1 scalar; 3 a vector field, CG or
+   * DG, in F64 or F32 only (else UNSUPPORTED).  Every vector of the operator then
    * holds the components one after another, [n_components][n_dofs], and
    * A acts on each with the same coefficient; the kappa gradient of the
    * backward is the sum over the components.  tetmf_load_vector is

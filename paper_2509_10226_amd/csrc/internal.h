@@ -80,9 +80,9 @@ hipError_t launch_dg(const DGDev& d, int prec, int ndof, int nq, int nqf, const 
                      const void* kappa_cell, const void* kappa_face, void* v, hipStream_t s,
                      bool* supported, hipEvent_t* ev);
 // SIPG coefficient gradients (dkappa_cell [nq][n_cell], dkappa_face
-// [nqf][n_face], either may be NULL) of g^T A u.
+// [nqf][n_face], either may be NULL) of g^T A u; accumulate: add to them.
 hipError_t launch_dg_grad(const DGDev& d, int prec, int ndof, int nq, int nqf, const void* u, const void* g,
-                          void* dkc, void* dkf, hipStream_t s, bool* supported);
+                          void* dkc, void* dkf, bool accumulate, hipStream_t s, bool* supported);
 hipError_t launch_layout(int prec, int to_user, const int* cell_perm, int n_cell, int nq,
                          const void* src, void* dst, hipStream_t s);
 

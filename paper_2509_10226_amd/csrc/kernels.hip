@@ -1120,7 +1120,7 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
 template <typename T, int NDOF, int NQ, int NQF>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8)))
 dg_grad_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ gv, T* __restrict__ dkc,
-               T* __restrict__ dkf) {
+               T* __restrict__ dkf, int accumulate) {
   using TC = Tile<T, NDOF, NQ, 3>;
   using TF = Tile<T, NDOF, NQF, 4>;
   using M = Mfma<T>;
@@ -1181,7 +1181,7 @@ dg_grad_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ gv, T* __
         const T x_ = ag[i0 / 4][i0 % 4], y_ = ag[(i0 + 1) / 4][(i0 + 1) % 4], z_ = ag[(i0 + 2) / 4][(i0 + 2) % 4];
         const T val = s_qw[q] * (ux * (G0 * x_ + G1 * y_ + G2 * z_) + uy * (G1 * x_ + G3 * y_ + G4 * z_) +
                                  uz * (G2 * x_ + G4 * y_ + G5 * z_));
-        if (valid && q < NQ) dkc[(long)q * nc + cell] = val;
+        if (valid && q < NQ) dkc[(long)q * nc + cell] = accumulate ? dkc[(long)q * nc + cell] + val : val;
       }
     }
     if (!dkf) continue;
@@ -1247,7 +1247,7 @@ dg_grad_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ gv, T* __
           val = d.dirichlet ? omq * (-jg[k] * au_[k] - ju[k] * ag_[k] + T(2) * tau * ju[k] * jg[k]) : T(0);
         else
           val = omq * (-ag_[k] * ju[k] - jg[k] * au_[k] + tau * ju[k] * jg[k]);
-        if (writer && q < NQF) dkf[(long)q * nf + fidv] = val;
+        if (writer && q < NQF) dkf[(long)q * nf + fidv] = accumulate ? dkf[(long)q * nf + fidv] + val : val;
       }
     }
   }
@@ -1290,7 +1290,8 @@ hipError_t launch_dg_shape(const DGDev& d, int ndof, int nq, int nqf, const void
 }
 
 template <typename T, int NDOF, int NQ, int NQF>
-hipError_t launch_dg_grad_t(const DGDev& d, const void* u, const void* g, void* dkc, void* dkf, hipStream_t s) {
+hipError_t launch_dg_grad_t(const DGDev& d, const void* u, const void* g, void* dkc, void* dkf, bool acc,
+                            hipStream_t s) {
   using TC = Tile<T, NDOF, NQ, 3>;
   using TF = Tile<T, NDOF, NQF, 4>;
   const size_t lds = (size_t)(TC::TAB + TF::TAB + TC::NPT + TF::NPT) * sizeof(T) + 24 * NDOF * sizeof(int);
@@ -1299,25 +1300,28 @@ hipError_t launch_dg_grad_t(const DGDev& d, const void* u, const void* g, void* 
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, (ntiles + kWaves - 1) / kWaves);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)g, (T*)dkc, (T*)dkf);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, d, (const T*)u, (const T*)g, (T*)dkc, (T*)dkf,
+                     acc ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_dg_grad_shape(const DGDev& d, int ndof, int nq, int nqf, const void* u, const void* g, void* dkc,
-                                void* dkf, hipStream_t s, bool* supported) {
+                                void* dkf, bool acc, hipStream_t s, bool* supported) {
   *supported = true;
-  if (ndof == 4 && nq == 4 && nqf == 3) return launch_dg_grad_t<T, 4, 4, 3>(d, u, g, dkc, dkf, s);
-  if (ndof == 10 && nq == 14 && nqf == 6) return launch_dg_grad_t<T, 10, 14, 6>(d, u, g, dkc, dkf, s);
-  if (ndof == 20 && nq == 24 && nqf == 12) return launch_dg_grad_t<T, 20, 24, 12>(d, u, g, dkc, dkf, s);
+  if (ndof == 4 && nq == 4 && nqf == 3) return launch_dg_grad_t<T, 4, 4, 3>(d, u, g, dkc, dkf, acc, s);
+  if (ndof == 10 && nq == 14 && nqf == 6) return launch_dg_grad_t<T, 10, 14, 6>(d, u, g, dkc, dkf, acc, s);
+  if (ndof == 20 && nq == 24 && nqf == 12) return launch_dg_grad_t<T, 20, 24, 12>(d, u, g, dkc, dkf, acc, s);
   *supported = false;
   return hipSuccess;
 }
 
 hipError_t launch_dg_grad(const DGDev& d, int prec, int ndof, int nq, int nqf, const void* u, const void* g,
-                          void* dkc, void* dkf, hipStream_t s, bool* supported) {
-  if (prec == PREC_F64) return launch_dg_grad_shape<double>(d, ndof, nq, nqf, u, g, dkc, dkf, s, supported);
-  if (prec == PREC_F32) return launch_dg_grad_shape<float>(d, ndof, nq, nqf, u, g, dkc, dkf, s, supported);
+                          void* dkc, void* dkf, bool accumulate, hipStream_t s, bool* supported) {
+  if (prec == PREC_F64)
+    return launch_dg_grad_shape<double>(d, ndof, nq, nqf, u, g, dkc, dkf, accumulate, s, supported);
+  if (prec == PREC_F32)
+    return launch_dg_grad_shape<float>(d, ndof, nq, nqf, u, g, dkc, dkf, accumulate, s, supported);
   *supported = false;
   return hipSuccess;
 }

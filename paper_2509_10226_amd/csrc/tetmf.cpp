@@ -1098,8 +1098,8 @@ int init_op(const tetmf_mesh* mesh, const tetmf_op_desc* d, tetmf_op* op, const 
   if (d->n_components != 0 && d->n_components != 1 && d->n_components != 3)
     return fail(TETMF_ERR_UNSUPPORTED, w + ": n_components must be 1 or 3");
   if (d->n_components == 3) {
-    if (op->kind != TETMF_CG || op->prec == TETMF_BF16IN)
-      return fail(TETMF_ERR_UNSUPPORTED, w + ": vector fields are supported for CG in FP64 and FP32 only");
+    if (op->prec == TETMF_BF16IN)
+      return fail(TETMF_ERR_UNSUPPORTED, w + ": vector fields are supported in FP64 and FP32 only");
     op->ncomp = 3;
   }
   if (d->q_jacobians) {
@@ -1278,10 +1278,15 @@ extern "C" int tetmf_apply(tetmf_op* op, const void* u, const void* kappa_cell, 
     }
     DeviceScope ds(op->device);
     bool supported = true;
-    hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, u, kappa_cell, kappa_face, v,
-                             (hipStream_t)stream, &supported, op->next_events());
-    if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
-    check_hip(e, "kernel launch");
+    // SIPG is cell-local: a vector field is one pass per component
+    const size_t cstride = (size_t)op->n_dofs * op->esize();
+    for (int c = 0; c < op->ncomp; ++c) {
+      hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, (const char*)u + c * cstride,
+                               kappa_cell, kappa_face, (char*)v + c * cstride, (hipStream_t)stream, &supported,
+                               op->next_events());
+      if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
+      check_hip(e, "kernel launch");
+    }
     return TETMF_OK;
   });
 }
@@ -1307,17 +1312,24 @@ extern "C" int tetmf_apply_backward(tetmf_op* op, const void* u, const void* g, 
     DeviceScope ds(op->device);
     hipStream_t s = (hipStream_t)stream;
     bool supported = true;
-    if (du) {
-      hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, g, kappa_cell, kappa_face, du, s,
-                               &supported, nullptr);
-      if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
-      check_hip(e, "kernel launch");
-    }
-    if (dkappa_cell || dkappa_face) {
-      hipError_t e = launch_dg_grad(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, u, g, dkappa_cell,
-                                    dkappa_face, s, &supported);
-      if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
-      check_hip(e, "kernel launch");
+    // vector fields: one pass per component; the coefficient gradients of
+    // the later components are added to the first one's (component order)
+    const size_t cstride = (size_t)op->n_dofs * op->esize();
+    for (int c = 0; c < op->ncomp; ++c) {
+      const char* uc = (const char*)u + c * cstride;
+      const char* gc = (const char*)g + c * cstride;
+      if (du) {
+        hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, gc, kappa_cell, kappa_face,
+                                 (char*)du + c * cstride, s, &supported, nullptr);
+        if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
+        check_hip(e, "kernel launch");
+      }
+      if (dkappa_cell || dkappa_face) {
+        hipError_t e = launch_dg_grad(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, uc, gc, dkappa_cell,
+                                      dkappa_face, c > 0, s, &supported);
+        if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
+        check_hip(e, "kernel launch");
+      }
     }
     return TETMF_OK;
   });

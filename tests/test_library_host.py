@@ -160,5 +160,5 @@ def test_vector_setup_checks():
     with pytest.raises(tm.TetmfError):
         tm.check_setup(mesh, 2, (qp, qw), precision="bf16in", n_components=3)
     fp, fw = synth.tri_rule(4)
-    with pytest.raises(tm.TetmfError):
-        tm.check_setup(mesh, 2, (qp, qw), kind="dg", frule=(fp, fw), n_components=3)
+    assert (tm.check_setup(mesh, 2, (qp, qw), kind="dg", frule=(fp, fw), n_components=3) ==
+            tm.check_setup(mesh, 2, (qp, qw), kind="dg", frule=(fp, fw)))
