@@ -1033,9 +1033,10 @@ void work_model(tetmf_op* op, const tetmf_mesh& m) {
   } else {
     const double nqf = op->nqf;
     const double nbf = (double)(m.nf - m.nif);
-    op->flops = fcell * m.nc + m.nif * (32 * nqf * nd + 46 * nqf) +
-                (op->bc == TETMF_DIRICHLET ? nbf * (16 * nqf * nd + 30 * nqf) : 0.0);
-    op->bytes = m.nc * (7 * s + s * nq + 20 + 2 * s * nd) + m.nf * (s * nqf + 8);
+    // a vector field runs one full pass per component
+    op->flops = op->ncomp * (fcell * m.nc + m.nif * (32 * nqf * nd + 46 * nqf) +
+                             (op->bc == TETMF_DIRICHLET ? nbf * (16 * nqf * nd + 30 * nqf) : 0.0));
+    op->bytes = op->ncomp * (m.nc * (7 * s + s * nq + 20 + 2 * s * nd) + m.nf * (s * nqf + 8));
   }
 }
 
