@@ -1407,7 +1407,7 @@ __global__ void dot_partial(const T* __restrict__ x, const T* __restrict__ y, lo
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
@@ -1420,7 +1420,7 @@ __global__ void dot_final(const double* __restrict__ part, int np, double* __res
   sh[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = sh[0];
@@ -1447,7 +1447,7 @@ __device__ inline double block_sum256(double v, double* sh) {
   sh[threadIdx.x] = v;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
   }
   const double r = sh[0];
