@@ -130,7 +130,8 @@ def time_graph(op, kl, u, steps, warmup, ref):
         ms = (time.perf_counter() - t0) * 1e3 / steps
         del graph
         return ms
-    except RuntimeError:
+    except Exception:  # capture unavailable: the eager time stands
+        torch.cuda.synchronize()
         return None
 
 
