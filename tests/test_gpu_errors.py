@@ -1,0 +1,104 @@
+"""Error results of the entry points as include/tetmf.h documents them,
+called through the C ABI on real operators: aliasing (ALIAS), arguments
+that do not fit the operator (INVALID_ARGUMENT), combinations without a
+kernel (UNSUPPORTED), and a solve that stops before its tolerance
+(NOT_CONVERGED, with the iterate left valid).  No kernel runs on invalid
+input: every case is rejected on the host before a launch."""
+import ctypes
+
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+OK, NOT_CONVERGED, INVALID, UNSUPPORTED, ALIAS = 0, 1, -1, -4, -5
+
+
+@pytest.fixture(scope="module")
+def ops():
+    import paper_2509_10226_amd as tm
+    xyz, tets = synth.kuhn_cube_mesh(3, 0.15, 0)
+    qp, qw = synth.tet_rule(4)
+    fp, fw = synth.tri_rule(4)
+    mesh = tm.Mesh(xyz, tets)
+    return dict(tm=tm, cg=tm.Operator(mesh, 2, (qp, qw), bc="dirichlet"),
+                bf=tm.Operator(mesh, 2, (qp, qw), bc="dirichlet", precision="bf16in"),
+                f32=tm.Operator(mesh, 2, (qp, qw), bc="dirichlet", precision="f32"),
+                dg=tm.Operator(mesh, 2, (qp, qw), kind="dg", frule=(fp, fw), bc="dirichlet"))
+
+
+def _p(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def test_apply_errors(ops):
+    tm = ops["tm"]
+    L, cg, dg = tm.lib(), ops["cg"], ops["dg"]
+    s = tm._stream()
+    u = torch.zeros(cg.n_vec, dtype=torch.float64, device="cuda")
+    v = torch.zeros_like(u)
+    assert L.tetmf_apply(cg._h, _p(u), None, None, _p(u), s) == ALIAS
+    kf = torch.ones(dg.n_qf * dg.n_face, dtype=torch.float64, device="cuda")
+    assert L.tetmf_apply(cg._h, _p(u), None, _p(kf), _p(v), s) == INVALID
+    assert L.tetmf_apply(cg._h, None, None, None, _p(v), s) == INVALID
+    assert L.tetmf_apply(cg._h, _p(u), None, None, _p(v), s) == OK
+
+
+def test_backward_errors(ops):
+    tm = ops["tm"]
+    L, cg, dg, bf = tm.lib(), ops["cg"], ops["dg"], ops["bf"]
+    s = tm._stream()
+    u = torch.zeros(cg.n_vec, dtype=torch.float64, device="cuda")
+    g = torch.zeros_like(u)
+    dk = torch.zeros(cg.n_q * cg.n_cell, dtype=torch.float64, device="cuda")
+    assert L.tetmf_apply_backward(cg._h, _p(u), _p(g), None, None, _p(u), None, None, s) == ALIAS
+    assert L.tetmf_apply_backward(cg._h, _p(u), _p(g), None, None, None, _p(dk), _p(dk), s) == INVALID
+    ud = torch.zeros(dg.n_vec, dtype=torch.float64, device="cuda")
+    gd = torch.zeros_like(ud)
+    dkc = torch.zeros(dg.n_q * dg.n_cell, dtype=torch.float64, device="cuda")
+    assert L.tetmf_apply_backward(dg._h, _p(ud), _p(gd), None, None, None, _p(dkc), _p(dkc), s) == ALIAS
+    ub = torch.zeros(bf.n_vec, dtype=torch.float32, device="cuda")
+    assert L.tetmf_apply_backward(bf._h, _p(ub), _p(ub.clone()), None, None, _p(ub.clone()), None, None,
+                                  s) == UNSUPPORTED
+
+
+def test_diagonal_load_layout_errors(ops):
+    tm = ops["tm"]
+    L, cg, dg = tm.lib(), ops["cg"], ops["dg"]
+    s = tm._stream()
+    d = torch.zeros(dg.n_vec, dtype=torch.float64, device="cuda")
+    assert L.tetmf_diagonal(dg._h, None, None, _p(d), s) == UNSUPPORTED
+    assert L.tetmf_load_vector(dg._h, None, _p(d), s) == UNSUPPORTED
+    x = torch.zeros(cg.n_q * cg.n_cell, dtype=torch.float64, device="cuda")
+    assert L.tetmf_cell_data_layout(cg._h, _p(x), _p(x), 0, s) == ALIAS
+
+
+def test_solve_errors_and_not_converged(ops):
+    tm = ops["tm"]
+    cg, f32 = ops["cg"], ops["f32"]
+    b = cg.load_vector().double()
+    with pytest.raises(tm.TetmfError) as e:
+        f32.solve(b)  # the outer operator must be FP64
+    assert e.value.status == INVALID
+    x, st, ok = cg.solve(b, rtol=1e-14, max_outer=1, max_inner=3)
+    assert not ok and st["final_relres"] > 1e-14
+    assert torch.isfinite(x).all()
+    x2, st2, ok2 = cg.solve(b, x0=x, rtol=1e-10)  # warm start from the stopped iterate
+    assert ok2 and st2["final_relres"] <= 1e-10
+
+
+def test_smoother_errors(ops):
+    tm = ops["tm"]
+    L, cg = tm.lib(), ops["cg"]
+    s = tm._stream()
+    b = torch.zeros(cg.n_vec, dtype=torch.float64, device="cuda")
+    inv = torch.ones_like(b)
+    assert L.tetmf_chebyshev(cg._h, None, _p(inv), _p(b), _p(b), 3, ctypes.c_double(0.1), ctypes.c_double(2.0), 0,
+                             s) == ALIAS
+    x = torch.zeros_like(b)
+    assert L.tetmf_chebyshev(cg._h, None, _p(inv), _p(b), _p(x), 3, ctypes.c_double(2.0), ctypes.c_double(1.0), 0,
+                             s) == INVALID
+    lam = ctypes.c_double()
+    assert L.tetmf_estimate_lambda_max(cg._h, None, _p(inv), 0, ctypes.byref(lam), s) == INVALID
