@@ -5,6 +5,8 @@ times, on outputs the oracle can compute one by one:
   FP64 / FP32 / BF16-operand apply against oracle rows (only the cells around
   each sampled DoF are assembled), and of the FP64 / FP32 apply on curved
   cells (the same mesh through a smooth map, a Jacobian per rule point);
+  the 3-component vector field, straight and curved: each component bitwise
+  equal to the scalar apply;
 * SIPG P3, 32^3 x 6 cells, lognormal(0, 0.5) cell and face coefficients,
   Dirichlet mirror: the rows of sampled cells;
 * CG P2 Helmholtz (stiffness + 1.0 mass), 48^3 x 6 cells: backward -- sampled
@@ -127,6 +129,24 @@ def test_f3_curved_sampled_rows(c3, precision, tol):
     err = np.abs(v[rows] - np.array(y)) / np.array(scale)
     print(f"F3 curved {precision}: max row error / sum|a u| = {err.max():.3e}")
     assert err.max() <= tol
+
+
+@pytest.mark.parametrize("curved", [False, True])
+def test_f2_vector_components_full_size(c3, curved):
+    """The vector field (3 components) at full size, as bench.py --config f2
+    runs it: every component of the apply is bitwise the scalar operator's
+    apply of that component (which the sampled-row tests above check against
+    the oracle), for straight and curved cells."""
+    tm = c3["tm"]
+    jac = synth.curved_jacobians(c3["xyz"], c3["tets"], c3["qp"], 0.25) if curved else None
+    opv = tm.Operator(c3["mesh"], 3, (c3["qp"], c3["qw"]), q_jacobians=jac, n_components=3)
+    ops = tm.Operator(c3["mesh"], 3, (c3["qp"], c3["qw"]), q_jacobians=jac)
+    kl = ops.cell_data_to_library(torch.from_numpy(c3["kap"]).to(DEV))
+    n = ops.n_dofs
+    u = torch.from_numpy(synth.uniform(2, synth.STREAM_U, 3 * n)).to(DEV)
+    v = opv.apply(u, kl)
+    for c in range(3):
+        assert torch.equal(v[c * n:(c + 1) * n], ops.apply(u[c * n:(c + 1) * n].contiguous(), kl))
 
 
 def test_c2_dg_sampled_cells():
