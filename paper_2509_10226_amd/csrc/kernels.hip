@@ -1441,6 +1441,10 @@ __global__ void sub_kernel(const double* __restrict__ b, const double* __restric
 // (each consuming block computes the identical total), so all scalars are
 // bitwise reproducible.
 constexpr int kVecBlocks = 512;
+// Elements per thread whose loads are issued together in the PCG vector
+// kernels; each thread still visits its elements in increasing index order,
+// so the per-thread sums are the same as with one element at a time.
+constexpr int kVecUnroll = 4;
 
 // Fixed-order sum over the block (256 threads) of v; the result in all threads.
 __device__ inline double block_sum256(double v, double* sh) {
@@ -1504,9 +1508,20 @@ template <typename T>
 __global__ void __launch_bounds__(256) pcg_dot_kernel(const T* __restrict__ a, const T* __restrict__ b,
                                                       double* __restrict__ part, long n) {
   __shared__ double sh[256];
+  constexpr long S = (long)kVecBlocks * 256;
   double v = 0;
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256)
-    v += (double)a[i] * (double)b[i];
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  for (; i + (kVecUnroll - 1) * S < n; i += kVecUnroll * S) {
+    T av[kVecUnroll], bv[kVecUnroll];
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      av[u] = a[i + u * S];
+      bv[u] = b[i + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) v += (double)av[u] * (double)bv[u];
+  }
+  for (; i < n; i += S) v += (double)a[i] * (double)b[i];
   v = block_sum256(v, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
@@ -1523,8 +1538,33 @@ __global__ void __launch_bounds__(256) pcg_xr_kernel(T* __restrict__ x, T* __res
   const double pq = sum_partials(part_pq, sh);
   if (pq_out && blockIdx.x == 0 && threadIdx.x == 0) *pq_out = pq;
   const T a = (T)(*rz / pq);
+  constexpr long S = (long)kVecBlocks * 256;
   double srz = 0, srr = 0;
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256) {
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  for (; i + (kVecUnroll - 1) * S < n; i += kVecUnroll * S) {
+    T xv[kVecUnroll], pv[kVecUnroll], rv[kVecUnroll], qv[kVecUnroll], dv[kVecUnroll];
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const long k = i + u * S;
+      xv[u] = x[k];
+      pv[u] = p[k];
+      rv[u] = r[k];
+      qv[u] = q[k];
+      dv[u] = dinv[k];
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      const long k = i + u * S;
+      x[k] = xv[u] + a * pv[u];
+      const T ri = rv[u] - a * qv[u];
+      const T zi = dv[u] * ri;
+      r[k] = ri;
+      z[k] = zi;
+      srz += (double)ri * (double)zi;
+      srr += (double)ri * (double)ri;
+    }
+  }
+  for (; i < n; i += S) {
     x[i] += a * p[i];
     const T ri = r[i] - a * q[i];
     const T zi = dinv[i] * ri;
@@ -1553,7 +1593,19 @@ __global__ void __launch_bounds__(256) pcg_p_kernel(T* __restrict__ p, const T* 
   __shared__ double sh[256];
   const double rzn = sum_partials(part_rz, sh);
   const T beta = (T)(rzn / *rz_old);
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256) p[i] = z[i] + beta * p[i];
+  constexpr long S = (long)kVecBlocks * 256;
+  long i = (long)blockIdx.x * 256 + threadIdx.x;
+  for (; i + (kVecUnroll - 1) * S < n; i += kVecUnroll * S) {
+    T zv[kVecUnroll], pv[kVecUnroll];
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) {
+      zv[u] = z[i + u * S];
+      pv[u] = p[i + u * S];
+    }
+#pragma unroll
+    for (int u = 0; u < kVecUnroll; ++u) p[i + u * S] = zv[u] + beta * pv[u];
+  }
+  for (; i < n; i += S) p[i] = z[i] + beta * p[i];
   if (blockIdx.x == 0) {
     const double rrn = sum_partials(part_rr, sh);
     if (threadIdx.x == 0) {
