@@ -769,31 +769,54 @@ __global__ void __launch_bounds__(kThreads) cg_vec_kernel(CGDev d, const T* __re
 // Shared DoFs: sum of the per-block partials in block order.  Constrained
 // DoFs: identity rows (apply/backward), 1 (diagonal), 0 (load vector).
 // blockIdx.y: the component of a vector field (partials, u and out offset by
-// one component each).
+// one component each).  Each thread takes kCombinePer entries i0, i0 + stride,
+// ... and issues their loads together: the slot ranges, then the first four
+// partial sums of each (at least two per shared DoF, checked at set-up).
+constexpr int kCombinePer = 2;
+
 template <typename T, int MODE>
 __global__ void __launch_bounds__(256) cg_combine(CGDev d, const T* __restrict__ u, T* __restrict__ out) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int stride = gridDim.x * 256;
+  const int i0 = blockIdx.x * 256 + threadIdx.x;
   const long cofs = (long)blockIdx.y * d.n_dofs;
   const T* part = static_cast<const T*>(d.partials) + (long)blockIdx.y * d.n_partials;
   if (u) u += cofs;
   out += cofs;
-  if (i < d.n_shared) {
-    // at least two partial sums per shared DoF (checked at set-up); the
-    // first four are loaded together, the sum keeps block order
-    const int p0 = d.sh_ptr[i], p1 = d.sh_ptr[i + 1];
-    const T a0 = part[p0], a1 = part[p0 + 1];
-    const T a2 = p0 + 2 < p1 ? part[p0 + 2] : T(0);
-    const T a3 = p0 + 3 < p1 ? part[p0 + 3] : T(0);
-    T s = 0;
-    s += a0;
-    s += a1;
-    if (p0 + 2 < p1) s += a2;
-    if (p0 + 3 < p1) s += a3;
-    for (int p = p0 + 4; p < p1; ++p) s += part[p];
-    out[d.sh_gid[i]] = s;
-  } else {
-    const int c = i - d.n_shared;
-    if (c < d.n_dofs - d.n_free) {
+  if (d.n_shared > 0) {
+    // entries past the shared DoFs load the last one's range (in bounds) and
+    // store nothing
+    int p0[kCombinePer], p1[kCombinePer], gid[kCombinePer];
+    T a[kCombinePer][4];
+#pragma unroll
+    for (int k = 0; k < kCombinePer; ++k) {
+      const int i = min(i0 + k * stride, d.n_shared - 1);
+      p0[k] = d.sh_ptr[i];
+      p1[k] = d.sh_ptr[i + 1];
+      gid[k] = d.sh_gid[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kCombinePer; ++k) {
+      a[k][0] = part[p0[k]];
+      a[k][1] = part[p0[k] + 1];
+      a[k][2] = p0[k] + 2 < p1[k] ? part[p0[k] + 2] : T(0);
+      a[k][3] = p0[k] + 3 < p1[k] ? part[p0[k] + 3] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < kCombinePer; ++k) {
+      if (i0 + k * stride >= d.n_shared) continue;
+      T s = 0;
+      s += a[k][0];
+      s += a[k][1];
+      if (p0[k] + 2 < p1[k]) s += a[k][2];
+      if (p0[k] + 3 < p1[k]) s += a[k][3];
+      for (int p = p0[k] + 4; p < p1[k]; ++p) s += part[p];
+      out[gid[k]] = s;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kCombinePer; ++k) {
+    const int c = i0 + k * stride - d.n_shared;
+    if (c >= 0 && c < d.n_dofs - d.n_free) {
       const int gi = d.n_free + c;
       out[gi] = (MODE == MODE_APPLY || MODE == MODE_BACKWARD) ? u[gi] : (MODE == MODE_DIAG ? T(1) : T(0));
     }
@@ -804,8 +827,8 @@ template <typename T, int MODE>
 hipError_t launch_combine(const CGDev& d, const void* src, void* out, hipStream_t s, int ncomp = 1) {
   const int nfix = d.n_shared + (d.n_dofs - d.n_free);
   if (nfix > 0)
-    hipLaunchKernelGGL((cg_combine<T, MODE>), dim3((nfix + 255) / 256, ncomp), dim3(256), 0, s, d, (const T*)src,
-                       (T*)out);
+    hipLaunchKernelGGL((cg_combine<T, MODE>), dim3((nfix + 256 * kCombinePer - 1) / (256 * kCombinePer), ncomp),
+                       dim3(256), 0, s, d, (const T*)src, (T*)out);
   return hipGetLastError();
 }
 
