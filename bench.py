@@ -38,6 +38,10 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "DoFs/s per operator apply, p=3 CG, FP64 vs FP32-MFMA; % of roofline"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "cg_apply_p3_n64_traffic.txt")
 TRAFFIC_FILE_CURVED = os.path.join(ROOT, "profiles", "cg_curved_p3_n64_traffic.txt")
+# The counter summaries cover the CG P3 cell kernel on the 64^3 x 6 mesh: the
+# straight-sided apply ("apply") and the curved-cell apply ("curved").
+TRAFFIC_FILES = {"apply": TRAFFIC_FILE, "curved": TRAFFIC_FILE_CURVED}
+PROFILED_CELLS = 6 * 64 ** 3
 KERNEL_SRC = os.path.join(ROOT, "paper_2509_10226_amd", "csrc", "kernels.hip")
 
 
@@ -139,12 +143,15 @@ def roofline(op, prec, avg_ms, traffic_key=None):
     """Roofline of the cell kernel, bound chosen by the algorithmic intensity
     (flops per byte) against the ridge point peak flops / peak HBM bandwidth:
     straight-sided FP64 and FP32 are compute-bound; BF16 operands (16x the
-    matrix-core peak) and curved cells (a geometry per point) are HBM-bound."""
+    matrix-core peak) and curved cells (a geometry per point) are HBM-bound.
+    traffic: the calibrated HBM bytes per launch of the counter summary that
+    traffic_key names, only on the mesh those counters were taken on; None
+    for every other kernel or workload."""
     flops = op.info["flops_per_apply"]
     bytes_alg = op.info["bytes_per_apply"]
     achieved = flops / (avg_ms * 1e-3) / 1e12
-    traffic = {None: lambda: read_traffic(prec), "curved": lambda: read_traffic(prec, TRAFFIC_FILE_CURVED)}.get(
-        traffic_key, lambda: None)()
+    path = TRAFFIC_FILES.get(traffic_key)
+    traffic = read_traffic(prec, path) if path and op.n_cell == PROFILED_CELLS else None
     gbs = bytes_alg / (avg_ms * 1e-3) / 1e9
     ridge = PEAK_TFLOPS[prec] * 1e12 / (PEAK_HBM_GBS * 1e9)
     if flops / bytes_alg < ridge:
@@ -396,7 +403,8 @@ def bench_f1(args):
             ms_step, ms_kernel, _ = time_gpu(op, kl, u, args.steps, args.warmup)
             res[f"degree{deg}_{prec}"] = {"n_q": int(qw.size), "DoFs_per_s": round(op.n_dofs / (ms_step * 1e-3), 1),
                                           "ms_per_step": round(ms_step, 5), "kernel_ms": round(ms_kernel, 5),
-                                          "roofline": roofline(op, prec, ms_kernel)}
+                                          "roofline": roofline(op, prec, ms_kernel,
+                                                               traffic_key="apply" if deg == 6 else None)}
             del op
     print(json.dumps({"metric": "DoFs/s per operator apply, CG P3, degree-4 (reduced) vs degree-6 cell rule",
                       "unit": "DoFs/s", "config": {"workload": f"CG P3 Poisson, {args.n}^3x6 Kuhn tets, lognormal(0,1) "
@@ -427,7 +435,7 @@ def bench_f2(args):
             g = torch.Generator(device="cpu").manual_seed(2)
             u = (torch.rand(opv.n_vec, generator=g, dtype=torch.float64) * 2 - 1).to("cuda", opv.dtype)
             ms_v, k_v, _ = time_gpu(opv, kl, u, args.steps, args.warmup)
-            rv = roofline(opv, prec, k_v, traffic_key="vector")
+            rv = roofline(opv, prec, k_v)
             del opv
             ops = tm.Operator(mesh, 3, (qp, qw), precision=prec, q_jacobians=qj)
             n = ops.n_dofs
@@ -470,7 +478,7 @@ def bench_f3(args):
             res[f"{'curved' if curved else 'straight'}_{prec}"] = {
                 "DoFs_per_s": round(op.n_dofs / (ms_step * 1e-3), 1), "ms_per_step": round(ms_step, 5),
                 "kernel_ms": round(ms_kernel, 5), "device_bytes": op.info["device_bytes"],
-                "roofline": roofline(op, prec, ms_kernel, traffic_key="curved" if curved else None)}
+                "roofline": roofline(op, prec, ms_kernel, traffic_key="curved" if curved else "apply")}
             del op
     print(json.dumps({"metric": "DoFs/s per operator apply, CG P3 on curved cells (per-point Jacobians)",
                       "value": res["curved_f64"]["DoFs_per_s"], "unit": "DoFs/s", "dtype": "f64",
@@ -567,7 +575,7 @@ def main():
             "ms_per_step": ms_step,
             "ms_per_step_eager": ms_eager,
             "timing": "graph" if ms_graph is not None else "eager",
-            "roofline": roofline(op, prec, ms_kernel),
+            "roofline": roofline(op, prec, ms_kernel, traffic_key="apply"),
             "n_dofs": op.n_dofs,
             "n_cell": op.n_cell,
             "setup_s": round(setup_s, 2),
