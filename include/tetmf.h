@@ -121,6 +121,8 @@ typedef struct {
   double bytes_per_apply;  /* algorithmic HBM bytes of one apply */
   int64_t device_bytes;    /* device memory held by the op */
   int32_t n_components;    /* 1, or 3 for a vector field (vectors hold n_components * n_dofs values) */
+  double flops_per_backward; /* algorithmic work of one tetmf_apply_backward with every output */
+  double bytes_per_backward;
 } tetmf_info;
 
 /* Mesh setup (Sec. 2.2 geometry; faces for eq. (7)).
@@ -134,16 +136,25 @@ void tetmf_mesh_destroy(tetmf_mesh* mesh);
 /* Number of faces (canonical order) and of interior faces. */
 int tetmf_mesh_faces(const tetmf_mesh* mesh, int64_t* n_face, int64_t* n_interior);
 
-/* Operator setup: DoF numbering, cell blocks, geometry G_e = |det J| J^{-1}
- * J^{-T} computed in FP64 and rounded to the op precision, basis tables,
- * face data.  Allocates device memory (OUT_OF_MEMORY on failure).
- * UNSUPPORTED for a (degree, n_q, n_qf, precision, kind) combination with no
- * compiled kernel, and for meshes beyond the kernels' 32-bit indexing
- * (n_dof_cell x n_cell, rounded up to whole 256-cell blocks for CG and to
- * 16-cell tiles for DG, must stay below 2^31: about 107 million cells at
- * P3).  The mesh may be destroyed afterwards. */
+/* Operator setup (Sec. 2.2: the precomputed geometry of each cell, J^{-1}
+ * and |det J| folded into G_e = |det J| J^{-1} J^{-T} as the factor of eq.
+ * (5); the tabulated basis matrices E of eq. (6); for SIPG the face data of
+ * eq. (7)): DoF numbering, cell blocks, geometry computed in FP64 and rounded
+ * to the op precision, basis tables, face data.  Allocates device memory
+ * (OUT_OF_MEMORY on failure).  UNSUPPORTED for a (degree, n_q, n_qf,
+ * precision, kind) combination with no compiled kernel, and for meshes
+ * beyond the kernels' 32-bit indexing: n_dof_cell x n_cell, rounded up to
+ * whole 256-cell blocks for CG and to 16-cell tiles for DG, must stay below
+ * 2^31 (about 107 million cells at P3); CG also needs at most 2^27 cells
+ * (rounded up to blocks) and n_dofs x element size below 2^32.  The mesh may
+ * be destroyed afterwards. */
 int tetmf_op_create(const tetmf_mesh* mesh, const tetmf_op_desc* desc, tetmf_op** out);
 void tetmf_op_destroy(tetmf_op* op);
+/* Sizes of the op and the algorithmic work of one apply and one backward:
+ * the flop count of eq. (9) extended by the per-point coefficient (and the
+ * mass term), with the DG face terms of eq. (11) counted per face, and the
+ * HBM bytes of eq. (8) for the stored geometry, indices, coefficients and
+ * vectors (each read or written once).  info: host, caller-owned. */
 int tetmf_op_info(const tetmf_op* op, tetmf_info* info);
 
 /* Host-only set-up check: runs the set-up of tetmf_op_create (numbering,
@@ -194,12 +205,19 @@ int tetmf_apply_backward(tetmf_op* op, const void* u, const void* g, const void*
                          const void* kappa_face, void* du, void* dkappa_cell, void* dkappa_face,
                          void* stream);
 
-/* d = diag(A(kappa)) (CG), constrained entries 1.  Device [n_components * n_dofs]. */
+/* d = diag(A(kappa)) (CG), constrained entries 1: the point Jacobi
+ * preconditioner of the conjugate-gradient and Chebyshev iterations of Sec.
+ * 4.1, from the diagonal entries of the cell matrices of eq. (5) summed per
+ * DoF.  kappa_cell as for tetmf_apply; kappa_face must be NULL (SIPG:
+ * UNSUPPORTED).  d: device [n_components * n_dofs] in the op precision. */
 int tetmf_diagonal(tetmf_op* op, const void* kappa_cell, const void* kappa_face, void* d, void* stream);
 
-/* Load vector b_i = sum_e sum_q w_q |det J| f_{e,q} phi_i(x_q) (CG), zero on
- * constrained rows.  f: device [n_q][n_cell] in the op precision or NULL
- * (f = 1).  b: device [n_dofs]. */
+/* Load vector: the right-hand side b(phi_i) of eq. (2) for the source f of
+ * eq. (1), b_i = (f, phi_i) =
+ * sum_e sum_q w_q |det J| f_{e,q} phi_i(x_q) (CG), with the cell rule of the
+ * operator; zero on constrained rows.  f: device [n_q][n_cell] in the op
+ * precision or NULL (f = 1).  b: device [n_dofs].  UNSUPPORTED for SIPG and
+ * for vector fields. */
 int tetmf_load_vector(tetmf_op* op, const void* f, void* b, void* stream);
 
 typedef struct {
@@ -275,6 +293,10 @@ int tetmf_estimate_lambda_max(tetmf_op* op, const void* kappa_cell, const void* 
  * summed kernel time in milliseconds and the number of launches recorded. */
 int tetmf_op_profile(tetmf_op* op, int enable);
 int tetmf_op_profile_read(tetmf_op* op, double* total_ms, int64_t* launches);
+/* The same measurement launch by launch: ms (host [capacity]) receives the
+ * duration of each of the first min(capacity, launches) recorded launches
+ * in recording order; *launches the number recorded.  Synchronises. */
+int tetmf_op_profile_times(tetmf_op* op, double* ms, int64_t capacity, int64_t* launches);
 
 const char* tetmf_status_string(int status);
 const char* tetmf_last_error(void);

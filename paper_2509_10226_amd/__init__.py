@@ -52,6 +52,7 @@ class Info(ctypes.Structure):
         ("n_blocks", ctypes.c_int64), ("n_shared", ctypes.c_int64), ("n_partials", ctypes.c_int64),
         ("flops_per_apply", ctypes.c_double), ("bytes_per_apply", ctypes.c_double),
         ("device_bytes", ctypes.c_int64), ("n_components", ctypes.c_int32),
+        ("flops_per_backward", ctypes.c_double), ("bytes_per_backward", ctypes.c_double),
     ]
 
 
@@ -95,6 +96,8 @@ _SIGS = {
     "tetmf_op_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "tetmf_op_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                              ctypes.POINTER(ctypes.c_int64)]),
+    "tetmf_op_profile_times": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                              ctypes.POINTER(ctypes.c_int64)]),
     "tetmf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "tetmf_last_error": (ctypes.c_char_p, []),
 }
@@ -127,17 +130,20 @@ def _torch():
     return torch
 
 
-def _stream():
+def _stream(device=None):
+    """The current torch stream of ``device`` (default: the current device)."""
     torch = _torch()
-    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def _ptr(t, dtype=None, numel=None, name="tensor"):
+def _ptr(t, dtype=None, numel=None, name="tensor", device=None):
     if t is None:
         return None
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name} is on {t.device}, the operator on cuda:{device}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if dtype is not None and t.dtype != dtype:
@@ -266,6 +272,10 @@ class Operator:
         _check(lib().tetmf_op_numbering(self._h, cp.ctypes.data, xyz.ctypes.data, dc.ctypes.data))
         return cp, xyz, dc
 
+    def _p(self, t, dtype=None, numel=None, name="tensor"):
+        """Device pointer of a tensor on the operator's device."""
+        return _ptr(t, dtype, numel, name, self.device)
+
     def _device(self):
         torch = _torch()
         return torch.device("cuda", self.device)
@@ -277,24 +287,24 @@ class Operator:
         if src.shape != (self.n_cell, self.n_q):
             raise ValueError(f"expected [{self.n_cell}, {self.n_q}]")
         dst = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_cell_data_layout(self._h, _ptr(src), _ptr(dst), 0, _stream()))
+        _check(lib().tetmf_cell_data_layout(self._h, self._p(src), self._p(dst), 0, _stream(self.device)))
         return dst
 
     def cell_data_to_user(self, data_lib):
         torch = _torch()
         dst = torch.empty((self.n_cell, self.n_q), dtype=torch.float64, device=self._device())
-        _check(lib().tetmf_cell_data_layout(self._h, _ptr(data_lib, self.dtype, self.n_cell * self.n_q),
-                                            _ptr(dst), 1, _stream()))
+        _check(lib().tetmf_cell_data_layout(self._h, self._p(data_lib, self.dtype, self.n_cell * self.n_q),
+                                            self._p(dst), 1, _stream(self.device)))
         return dst
 
     def apply(self, u, kappa_cell=None, kappa_face=None, out=None):
         torch = _torch()
         if out is None:
             out = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_apply(self._h, _ptr(u, self.dtype, self.n_vec, "u"),
-                                 _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
-                                 _ptr(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
-                                 _ptr(out, self.dtype, self.n_vec, "v"), _stream()))
+        _check(lib().tetmf_apply(self._h, self._p(u, self.dtype, self.n_vec, "u"),
+                                 self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                 self._p(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
+                                 self._p(out, self.dtype, self.n_vec, "v"), _stream(self.device)))
         return out
 
     def backward(self, u, g, kappa_cell=None, need_du=True, need_dkappa=True, kappa_face=None,
@@ -307,25 +317,25 @@ class Operator:
         du = torch.empty(self.n_vec, dtype=self.dtype, device=dev) if need_du else None
         dk = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=dev) if need_dkappa else None
         dkf = torch.empty((self.n_qf, self.n_face), dtype=self.dtype, device=dev) if need_dkappa_face else None
-        _check(lib().tetmf_apply_backward(self._h, _ptr(u, self.dtype, self.n_vec, "u"),
-                                          _ptr(g, self.dtype, self.n_vec, "g"),
-                                          _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
-                                          _ptr(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
-                                          _ptr(du), _ptr(dk), _ptr(dkf), _stream()))
+        _check(lib().tetmf_apply_backward(self._h, self._p(u, self.dtype, self.n_vec, "u"),
+                                          self._p(g, self.dtype, self.n_vec, "g"),
+                                          self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                          self._p(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
+                                          self._p(du), self._p(dk), self._p(dkf), _stream(self.device)))
         return (du, dk, dkf) if need_dkappa_face else (du, dk)
 
     def diagonal(self, kappa_cell=None):
         torch = _torch()
         d = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_diagonal(self._h, _ptr(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
-                                    None, _ptr(d), _stream()))
+        _check(lib().tetmf_diagonal(self._h, self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                    None, self._p(d), _stream(self.device)))
         return d
 
     def load_vector(self, f=None):
         torch = _torch()
         b = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_load_vector(self._h, _ptr(f, self.dtype, self.n_q * self.n_cell, "f"), _ptr(b),
-                                       _stream()))
+        _check(lib().tetmf_load_vector(self._h, self._p(f, self.dtype, self.n_q * self.n_cell, "f"), self._p(b),
+                                       _stream(self.device)))
         return b
 
     def solve(self, b, x0=None, kappa=None, inner=None, kappa_inner=None, rtol=1e-10, inner_rtol=1e-4,
@@ -336,11 +346,11 @@ class Operator:
         o = SolveOpts(rtol, inner_rtol, max_outer, max_inner, 1 if precond == "jacobi" else 0)
         st = SolveStats()
         status = _check(lib().tetmf_solve(
-            self._h, _ptr(kappa, torch.float64, self.n_q * self.n_cell, "kappa"),
+            self._h, self._p(kappa, torch.float64, self.n_q * self.n_cell, "kappa"),
             inner._h if inner is not None else None,
-            _ptr(kappa_inner, inner.dtype if inner is not None else None, None, "kappa_inner"),
-            _ptr(b, torch.float64, self.n_vec, "b"), _ptr(x, torch.float64, self.n_vec, "x"),
-            ctypes.byref(o), ctypes.byref(st), _stream()))
+            self._p(kappa_inner, inner.dtype if inner is not None else None, None, "kappa_inner"),
+            self._p(b, torch.float64, self.n_vec, "b"), self._p(x, torch.float64, self.n_vec, "x"),
+            ctypes.byref(o), ctypes.byref(st), _stream(self.device)))
         stats = {k: getattr(st, k) for k, _ in SolveStats._fields_}
         return x, stats, status == 0
 
@@ -352,19 +362,19 @@ class Operator:
         zero = x is None
         if zero:
             x = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_chebyshev(self._h, _ptr(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
-                                     _ptr(inv_diag, self.dtype, self.n_vec, "inv_diag"),
-                                     _ptr(b, self.dtype, self.n_vec, "b"), _ptr(x, self.dtype, self.n_vec, "x"),
-                                     int(degree), float(lambda_min), float(lambda_max), 1 if zero else 0, _stream()))
+        _check(lib().tetmf_chebyshev(self._h, self._p(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
+                                     self._p(inv_diag, self.dtype, self.n_vec, "inv_diag"),
+                                     self._p(b, self.dtype, self.n_vec, "b"), self._p(x, self.dtype, self.n_vec, "x"),
+                                     int(degree), float(lambda_min), float(lambda_max), 1 if zero else 0, _stream(self.device)))
         return x
 
     def estimate_lambda_max(self, inv_diag, n_iter=20, kappa=None):
         """Lanczos estimate of the largest eigenvalue of D^-1 A (see
         tetmf_estimate_lambda_max)."""
         lam = ctypes.c_double()
-        _check(lib().tetmf_estimate_lambda_max(self._h, _ptr(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
-                                               _ptr(inv_diag, self.dtype, self.n_vec, "inv_diag"), int(n_iter),
-                                               ctypes.byref(lam), _stream()))
+        _check(lib().tetmf_estimate_lambda_max(self._h, self._p(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
+                                               self._p(inv_diag, self.dtype, self.n_vec, "inv_diag"), int(n_iter),
+                                               ctypes.byref(lam), _stream(self.device)))
         return lam.value
 
 
@@ -378,8 +388,15 @@ def _profile_methods():
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(lib().tetmf_op_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+    def profile_times(self, capacity=4096):
+        """Milliseconds of each recorded main-kernel launch (numpy array)."""
+        ms = np.empty(capacity, dtype=np.float64)
+        n = ctypes.c_int64()
+        _check(lib().tetmf_op_profile_times(self._h, ms.ctypes.data, capacity, ctypes.byref(n)))
+        return ms[:min(n.value, capacity)].copy()
     Operator.profile = profile
     Operator.profile_read = profile_read
+    Operator.profile_times = profile_times
 
 
 _profile_methods()
@@ -395,11 +412,14 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, u, kappa, kappa_face, op):
+            # the contiguous tensors the apply reads are the ones the backward
+            # reads again
+            u, kappa = u.contiguous(), kappa.contiguous()
+            kappa_face = kappa_face.contiguous() if kappa_face is not None else None
             ctx.op = op
             ctx.has_face = kappa_face is not None
             ctx.save_for_backward(u, kappa, kappa_face)
-            return op.apply(u.contiguous(), kappa.contiguous(),
-                            kappa_face.contiguous() if kappa_face is not None else None)
+            return op.apply(u, kappa, kappa_face)
 
         @staticmethod
         def backward(ctx, gv):

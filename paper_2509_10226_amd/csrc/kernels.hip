@@ -507,7 +507,9 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
             const int w = i * kThreads + st;
             const int j = (2 * w) / kBlockCells, cl = (2 * w) % kBlockCells;
             // word (j ncp + b kBlockCells + cl) / 2: block base + 32-bit byte offset
-            wv[i] = w < W ? load_at(src + (long)b * (kBlockCells / 2), (uint32_t)(2 * (j * ncp + cl))) : 0u;
+            wv[i] = w < W ? load_at(src + (long)b * (kBlockCells / 2),
+                                    2u * ((uint32_t)j * (uint32_t)ncp + (uint32_t)cl))
+                          : 0u;
           }
         }
         // DoF values: all index loads first, then all value loads (clamped
@@ -583,8 +585,11 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
             if (4 * k + 3 < NQ) {
               kq[k] = load_at(kappa + (long)(4 * k) * nc, kof);
             } else {
+              // partly used last group: row base 4k, lane row q - 4k < 4, so
+              // the 32-bit offset stays below 4 nc sizeof(T), as in the full groups
               const int q = min(g + 4 * k, NQ - 1);
-              kq[k] = load_at(kappa, ((uint32_t)q * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T));
+              kq[k] = load_at(kappa + (long)(4 * k) * nc,
+                              ((uint32_t)(q - 4 * k) * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T));
             }
           }
         } else {

@@ -361,7 +361,8 @@ struct tetmf_op {
   int32_t* d_cell_perm = nullptr;
   CGDev cg{};
   DGDev dg{};
-  double flops = 0, bytes = 0;
+  double flops = 0, bytes = 0;          // algorithmic work of one apply
+  double flops_bwd = 0, bytes_bwd = 0;  // and of one full backward
   int ncomp = 1;                 // components of a vector field (CG), stored one after another
   bool curved = false;
   const double* qjac = nullptr;  // per-point Jacobians during set-up only (user memory)
@@ -701,10 +702,13 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
   const int64_t nb = (nc + kBlockCells - 1) / kBlockCells;
   op->n_blocks = nb;
   op->ncp = nb * kBlockCells;
-  // the kernels address the [n_dof][ncp] index arrays with 32-bit integers
-  if ((int64_t)nd * op->ncp > INT32_MAX)
-    throw Error(TETMF_ERR_UNSUPPORTED, "mesh too large for one operator: at most " +
-                                           std::to_string(INT32_MAX / nd / kBlockCells * kBlockCells) +
+  // the kernels address the [n_dof][ncp] index arrays with 32-bit integers,
+  // and read per-cell data with a 32-bit byte offset from a row base: at
+  // most 4 rows of ncp values of 8 bytes (coefficients, geometry) or 16 rows
+  // of 2-byte indices, i.e. below 32 ncp bytes
+  const int64_t max_cells = std::min<int64_t>(INT32_MAX / nd, (int64_t)1 << 27) / kBlockCells * kBlockCells;
+  if (op->ncp > max_cells)
+    throw Error(TETMF_ERR_UNSUPPORTED, "mesh too large for one operator: at most " + std::to_string(max_cells) +
                                            " cells at this degree (32-bit indexing)");
   std::vector<int32_t> bmin(ntmp, INT32_MAX), bmax(ntmp, -1);
   for (int64_t i = 0; i < nc; ++i) {
@@ -750,6 +754,9 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
     }
   op->n_dofs = next;
   if (op->n_dofs > INT32_MAX) throw Error(TETMF_ERR_UNSUPPORTED, "more than 2^31 DoFs");
+  // DoF values are staged with a 32-bit byte offset from the vector's start
+  if ((uint64_t)op->n_dofs * op->esize() > UINT32_MAX)
+    throw Error(TETMF_ERR_UNSUPPORTED, "too many DoFs for 32-bit byte offsets at this precision");
   // DoF coordinates and one containing cell
   op->dof_xyz.assign((size_t)3 * op->n_dofs, 0.0);
   op->dof_cell.assign(op->n_dofs, -1);
@@ -1030,6 +1037,11 @@ void work_model(tetmf_op* op, const tetmf_mesh& m) {
     const double ng = (mass ? 7 : 6) * (op->curved ? nq : 1.0);
     op->flops = fcell * m.nc * op->ncomp;
     op->bytes = m.nc * (ng * s + 4 * nd + s * nq) + 2 * s * (double)op->nvec();
+    // backward: u and g interpolated, D applied to g and integrated (du),
+    // plus w_q grad u . G grad g per point (21 flops); kappa read, dkappa
+    // written, u and g read, du written
+    op->flops_bwd = (6 * r * nq * nd + (cq + 21) * nq + nd) * m.nc * op->ncomp;
+    op->bytes_bwd = m.nc * (ng * s + 4 * nd + 2 * s * nq) + 3 * s * (double)op->nvec();
   } else {
     const double nqf = op->nqf;
     const double nbf = (double)(m.nf - m.nif);
@@ -1037,6 +1049,17 @@ void work_model(tetmf_op* op, const tetmf_mesh& m) {
     op->flops = op->ncomp * (fcell * m.nc + m.nif * (32 * nqf * nd + 46 * nqf) +
                              (op->bc == TETMF_DIRICHLET ? nbf * (16 * nqf * nd + 30 * nqf) : 0.0));
     op->bytes = op->ncomp * (m.nc * (7 * s + s * nq + 20 + 2 * s * nd) + m.nf * (s * nqf + 8));
+    // backward: du = A g (one apply) and the coefficient-gradient pass, which
+    // interpolates u and g at the cell points (21 flops each for dkappa) and
+    // both traces of u and g at the face points (4 values of nd terms per
+    // side and field), with about 30 (interior) / 20 (boundary) flops of the
+    // flux bracket per face point; it reads both coefficients and writes
+    // their gradients
+    const double fgrad = m.nc * (4 * r * nq * nd + 21 * nq) + m.nif * (32 * nqf * nd + 30 * nqf) +
+                         (op->bc == TETMF_DIRICHLET ? nbf * (16 * nqf * nd + 20 * nqf) : 0.0);
+    const double bgrad = m.nc * (7 * s + 2 * s * nq + 20 + 2 * s * nd) + m.nf * (2 * s * nqf + 8);
+    op->flops_bwd = op->flops + op->ncomp * fgrad;
+    op->bytes_bwd = op->bytes + op->ncomp * bgrad;
   }
 }
 
@@ -1206,6 +1229,8 @@ extern "C" int tetmf_op_info(const tetmf_op* op, tetmf_info* info) {
   info->flops_per_apply = op->flops;
   info->bytes_per_apply = op->bytes;
   info->device_bytes = op->device_bytes();
+  info->flops_per_backward = op->flops_bwd;
+  info->bytes_per_backward = op->bytes_bwd;
   return TETMF_OK;
 }
 
@@ -1665,6 +1690,22 @@ extern "C" int tetmf_op_profile_read(tetmf_op* op, double* total_ms, int64_t* la
       sum += ms;
     }
     *total_ms = sum;
+    *launches = (int64_t)op->events_used;
+    return TETMF_OK;
+  });
+}
+extern "C" int tetmf_op_profile_times(tetmf_op* op, double* ms, int64_t capacity, int64_t* launches) {
+  return guarded([&]() -> int {
+    if (!op || !ms || !launches || capacity < 0)
+      return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_op_profile_times: NULL argument or negative capacity");
+    DeviceScope ds(op->device);
+    const int64_t n = std::min<int64_t>((int64_t)op->events_used, capacity);
+    for (int64_t i = 0; i < n; ++i) {
+      check_hip(hipEventSynchronize(op->events[2 * i + 1]), "hipEventSynchronize");
+      float t = 0;
+      check_hip(hipEventElapsedTime(&t, op->events[2 * i], op->events[2 * i + 1]), "hipEventElapsedTime");
+      ms[i] = t;
+    }
     *launches = (int64_t)op->events_used;
     return TETMF_OK;
   });

@@ -174,8 +174,11 @@ def curved_jacobians(xyz, tets, qpts, eps):
     JK = np.stack([X[:, 1] - X[:, 0], X[:, 2] - X[:, 0], X[:, 3] - X[:, 0]], axis=2)
     P = X[:, None, 0, :] + np.einsum("eab,qb->eqa", JK, np.asarray(qpts, dtype=np.float64))
     x, y, z = P[..., 0], P[..., 1], P[..., 2]
-    one, zero = np.ones_like(x), np.zeros_like(x)
-    D = np.stack([np.stack([one, 2 * eps * y, zero], -1),
-                  np.stack([zero, one, 2 * eps * z], -1),
-                  np.stack([2 * eps * x, zero, one], -1)], -2)
-    return np.einsum("eqab,ebc->eqac", D, JK)
+    # D Phi = [[1, 2 eps y, 0], [0, 1, 2 eps z], [2 eps x, 0, 1]] times J_K,
+    # row by row (the zero and unit entries written out)
+    out = np.empty(P.shape[:2] + (3, 3))
+    J0, J1, J2 = JK[:, None, 0, :], JK[:, None, 1, :], JK[:, None, 2, :]
+    out[:, :, 0, :] = J0 + (2 * eps * y)[..., None] * J1
+    out[:, :, 1, :] = J1 + (2 * eps * z)[..., None] * J2
+    out[:, :, 2, :] = (2 * eps * x)[..., None] * J0 + J2
+    return out

@@ -34,3 +34,20 @@ def dg_map(op_xyz, op_cell, xyz, tets, p):
 
 def rel_err(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def row_err(v, A, u, idx=None):
+    """Largest entry-wise error of v against y = A u, each entry measured
+    against its row scale sum_j |a_ij| |u_j| (so a wrong entry in a
+    small-magnitude row is not hidden by the norm of the whole vector).
+    idx maps the entries of v to rows of A (library -> oracle numbering).
+    Rows with a zero scale must match exactly."""
+    y = A @ u
+    s = abs(A) @ np.abs(u)
+    if idx is not None:
+        y, s = y[idx], s[idx]
+    d = np.abs(np.asarray(v, dtype=np.float64) - y)
+    zero = s == 0
+    if np.any(d[zero] != 0):
+        return float("inf")
+    return float(np.max(d[~zero] / s[~zero])) if np.any(~zero) else 0.0
