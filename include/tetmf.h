@@ -189,6 +189,27 @@ int tetmf_cell_data_layout(const tetmf_op* op, const void* src, void* dst, int t
 int tetmf_apply(tetmf_op* op, const void* u, const void* kappa_cell, const void* kappa_face, void* v,
                 void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): v =
+ * A(kappa) u exactly as tetmf_apply computes it (the same kernels; the
+ * result is bitwise equal), with the CG interface partial sums (the
+ * op's only per-apply scratch) kept in a fixed device array of the library
+ * instead of the op's buffer.  The call allocates nothing and takes no
+ * profiling events.  The array is TETMF_NOALLOC_SCRATCH_BYTES long; every
+ * GPU the library runs on holds its own copy until the process ends, and
+ * its device address is resolved at tetmf_op_create.
+ *  Arguments, layouts and errors as for tetmf_apply, and UNSUPPORTED (no
+ *  kernel launched) when n_partials * n_components * element size exceeds
+ *  the array (the 64^3 x 6 P3 FP64 scalar operator needs 40 MB; its
+ *  three-component form 120 MB does not fit).
+ *  All calls on one GPU share the array and it keeps the last call's
+ *  contents: calls whose execution overlaps on one GPU (other streams, other
+ *  host threads) race and give wrong results; serialise them.  SIPG
+ *  operators use no scratch and run tetmf_apply's kernels. */
+#define TETMF_NOALLOC_SCRATCH_BYTES (64u << 20)
+int tetmf_apply_noalloc(tetmf_op* op, const void* u, const void* kappa_cell, const void* kappa_face, void* v,
+                        void* stream);
+
 /* Backward of v = A(kappa) u for an upstream gradient g = dL/dv: the
  * derivatives of the bilinear forms of eq. (5) / eq. (7) (the paper gives no
  * backward; these follow from differentiating the forms):

@@ -82,6 +82,7 @@ _SIGS = {
     "tetmf_cell_data_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                               ctypes.c_void_p]),
     "tetmf_apply": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 5),
+    "tetmf_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 5),
     "tetmf_apply_backward": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 8),
     "tetmf_diagonal": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
     "tetmf_load_vector": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
@@ -305,6 +306,15 @@ class Operator:
                                  self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
                                  self._p(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
                                  self._p(out, self.dtype, self.n_vec, "v"), _stream(self.device)))
+        return out
+
+    def apply_noalloc(self, u, out, kappa_cell=None, kappa_face=None):
+        """v = A(kappa) u into the caller's ``out`` with the library's fixed
+        scratch (tetmf_apply_noalloc): nothing is allocated."""
+        _check(lib().tetmf_apply_noalloc(self._h, self._p(u, self.dtype, self.n_vec, "u"),
+                                         self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                         self._p(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
+                                         self._p(out, self.dtype, self.n_vec, "v"), _stream(self.device)))
         return out
 
     def backward(self, u, g, kappa_cell=None, need_du=True, need_dkappa=True, kappa_face=None,

@@ -83,6 +83,9 @@ hipError_t launch_dg(const DGDev& d, int prec, int ndof, int nq, int nqf, const 
 // [nqf][n_face], either may be NULL) of g^T A u; accumulate: add to them.
 hipError_t launch_dg_grad(const DGDev& d, int prec, int ndof, int nq, int nqf, const void* u, const void* g,
                           void* dkc, void* dkf, bool accumulate, hipStream_t s, bool* supported);
+// Device address of the fixed scratch array on the current device (resolved
+// once per device, then cached); TETMF_NOALLOC_SCRATCH_BYTES long.
+hipError_t noalloc_scratch(void** ptr);
 hipError_t launch_layout(int prec, int to_user, const int* cell_perm, int n_cell, int nq,
                          const void* src, void* dst, hipStream_t s);
 

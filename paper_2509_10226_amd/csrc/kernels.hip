@@ -28,6 +28,9 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <mutex>
+
+#include "tetmf.h"
 
 namespace tetmf {
 
@@ -1793,6 +1796,37 @@ hipError_t vec_axpy_f64(double* x, const void* d, int prec_d, int64_t n, hipStre
   else
     hipLaunchKernelGGL(axpy64_kernel<float>, dim3(vgrid(n)), dim3(256), 0, s, x, (const float*)d, (long)n);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch of tetmf_apply_noalloc (callers that cannot allocate):
+// the interface partial sums of a CG apply live in this array instead of the
+// op's own buffer.  Every GPU the library runs on holds its own copy until
+// the process ends.  In host code the array's name is only a host-side
+// stand-in: noalloc_scratch() resolves the device address of the copy on the
+// current device once (hipGetSymbolAddress) and every later use takes that
+// address.  The partial sums need no clearing: the cell kernel writes every
+// one of them before the combine kernel reads it.
+static __device__ __align__(256) unsigned char scratch[TETMF_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace tetmf

@@ -1180,10 +1180,15 @@ extern "C" int tetmf_op_create(const tetmf_mesh* mesh, const tetmf_op_desc* d, t
     int st = init_op(mesh, d, op, "tetmf_op_create");
     if (st) return st;
     op->d_cell_perm = (int32_t*)op->upload(op->cell_perm);
-    if (op->kind == TETMF_CG)
+    if (op->kind == TETMF_CG) {
       setup_cg(op, *mesh, true);
-    else
+      // device address of the fixed scratch of tetmf_apply_noalloc on this
+      // device (resolved once per device, with the device current)
+      void* scr = nullptr;
+      check_hip(noalloc_scratch(&scr), "scratch symbol address");
+    } else {
       setup_dg(op, *mesh, true);
+    }
     fill_tables(op, d);
     work_model(op, *mesh);
     op->qjac = nullptr;
@@ -1313,6 +1318,45 @@ extern "C" int tetmf_apply(tetmf_op* op, const void* u, const void* kappa_cell, 
       if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
       check_hip(e, "kernel launch");
     }
+    return TETMF_OK;
+  });
+}
+
+extern "C" int tetmf_apply_noalloc(tetmf_op* op, const void* u, const void* kappa_cell, const void* kappa_face,
+                                   void* v, void* stream) {
+  return guarded([&]() -> int {
+    if (!op || !u || !v) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_apply_noalloc: NULL op or vector");
+    if (u == v) return fail(TETMF_ERR_ALIAS, "tetmf_apply_noalloc: u and v alias");
+    DeviceScope ds(op->device);
+    bool supported = true;
+    if (op->kind != TETMF_CG) {
+      // SIPG is cell-local and uses no scratch: the launches of tetmf_apply
+      const size_t cstride = (size_t)op->n_dofs * op->esize();
+      for (int c = 0; c < op->ncomp; ++c) {
+        hipError_t e = launch_dg(op->dg, kernel_prec(op), op->ndof, op->nq, op->nqf, (const char*)u + c * cstride,
+                                 kappa_cell, kappa_face, (char*)v + c * cstride, (hipStream_t)stream, &supported,
+                                 nullptr);
+        if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no DG kernel instantiation for this operator");
+        check_hip(e, "kernel launch");
+      }
+      return TETMF_OK;
+    }
+    if (kappa_face) return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_apply_noalloc: kappa_face given for a CG operator");
+    const uint64_t need = (uint64_t)op->n_partials * (uint64_t)op->ncomp * (uint64_t)op->esize();
+    if (need > (uint64_t)TETMF_NOALLOC_SCRATCH_BYTES)
+      return fail(TETMF_ERR_UNSUPPORTED, "tetmf_apply_noalloc: the operator needs " + std::to_string(need) +
+                                             " bytes of interface partial sums, more than the fixed scratch of " +
+                                             std::to_string((uint64_t)TETMF_NOALLOC_SCRATCH_BYTES) +
+                                             " bytes; use tetmf_apply");
+    void* scr = nullptr;
+    check_hip(noalloc_scratch(&scr), "scratch symbol address");
+    // the op's kernels with the partial sums in the fixed scratch
+    CGDev d = op->cg;
+    d.partials = scr;
+    hipError_t e = launch_cg(d, kernel_prec(op), op->ndof, op->nq, MODE_APPLY, u, nullptr, kappa_cell, v, nullptr,
+                             (hipStream_t)stream, &supported, nullptr);
+    if (!supported) return fail(TETMF_ERR_UNSUPPORTED, "no kernel instantiation for this operator");
+    check_hip(e, "kernel launch");
     return TETMF_OK;
   });
 }
