@@ -305,11 +305,11 @@ int tetmf_estimate_lambda_max(tetmf_op* op, const void* kappa_cell, const void* 
 
 /* Measurement aid.  While enabled, every launch of the op's main kernel (the
  * cell kernel of apply, backward, diagonal and load vector; the
- * cell-and-face kernel for DG) is bracketed by a HIP event pair on the
- * caller's stream: a marker recorded just before the kernel (it completes
- * when the preceding work has finished) and an event attached to the
- * kernel's dispatch for its end timestamp.  tetmf_op_profile(op, 1) starts a new measurement (events are created
- * on demand and reused), tetmf_op_profile(op, 0) stops recording.
+ * cell-and-face kernel for DG) carries a HIP event pair attached to its
+ * dispatch on the caller's stream, which records the dispatch's start and
+ * end timestamps (no extra packet between launches).  tetmf_op_profile(op,
+ * 1) starts a new measurement (events are created on demand and reused),
+ * tetmf_op_profile(op, 0) stops recording.
  * tetmf_op_profile_read synchronises on the recorded events and returns the
  * summed kernel time in milliseconds and the number of launches recorded. */
 int tetmf_op_profile(tetmf_op* op, int enable);

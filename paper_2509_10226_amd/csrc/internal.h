@@ -70,9 +70,8 @@ struct DGDev {
 };
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
-// ev: NULL, or two events: ev[0] recorded on s just before the main kernel
-// (it completes once the preceding work has finished), ev[1] attached to the
-// kernel's dispatch (hipExtLaunchKernelGGL) for its end timestamp.
+// ev: NULL, or two events attached to the main kernel's dispatch
+// (hipExtLaunchKernelGGL): its start and end timestamps.
 hipError_t launch_cg(const CGDev& d, int prec, int ndof, int nq, int mode, const void* u, const void* g,
                      const void* kappa, void* out, void* dkappa, hipStream_t s, bool* supported,
                      hipEvent_t* ev);

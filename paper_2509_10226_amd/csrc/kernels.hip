@@ -24,6 +24,7 @@
 // The E table lives in LDS ([point][component][NDOF+1], the odd stride keeps
 // the 16 lanes that read one column on distinct banks).
 #include "internal.h"
+#include "lane_map.h"
 
 #include <hip/hip_ext.h>
 
@@ -46,7 +47,7 @@ struct Mfma<double> {
   __device__ static inline acc_t mma(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
-  __device__ static constexpr int row(int g, int r) { return g + 4 * r; }
+  __device__ static constexpr int row(int g, int r) { return lanes::acc_row(8, g, r); }
   __device__ static constexpr int row_g(int i) { return i & 3; }
   __device__ static constexpr int row_r(int i) { return i >> 2; }
 };
@@ -57,7 +58,7 @@ struct Mfma<float> {
   __device__ static inline acc_t mma(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  __device__ static constexpr int row(int g, int r) { return 4 * g + r; }
+  __device__ static constexpr int row(int g, int r) { return lanes::acc_row(4, g, r); }
   __device__ static constexpr int row_g(int i) { return i >> 2; }
   __device__ static constexpr int row_r(int i) { return i & 3; }
 };
@@ -200,10 +201,30 @@ struct Tile {
   __device__ static inline void integrate(const T* __restrict__ s_tab, const acc_t (&acc)[MT], int g, int c16,
                                           acc_t& v, T (&vv)[NVA > 0 ? NVA : 1]) {
     v = acc_t{0, 0, 0, 0};
+    if constexpr (sizeof(T) == 8 && NDOF <= 12) {
+      // FP64 with at most 12 DoFs (P1, P2): the 16-row product would be at
+      // most three quarters full.  Instead, ceil(NDOF / 4) chains of the
+      // 4x4x4 four-block product (lane layout as for the tail below): chain
+      // r takes DoF 4r + (c16 & 3) as its A operand and delivers DoF 4r + g
+      // to lane group g, which is exactly accumulator element r of the
+      // 16-row layout (row g + 4r), at a quarter of its cost per chain.
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      const T a = (NMF == 16 || c16 < NMF) ? s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + c16] : T(0);
-      v = M::mma(a, acc[s / 4][s % 4], v);
+      for (int r = 0; r < (NDOF + 3) / 4; ++r) {
+        const int col = 4 * r + (c16 & 3);
+        T t = T(0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const T a = (NDOF % 4 == 0 || col < NDOF) ? s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + col] : T(0);
+          t = __builtin_amdgcn_mfma_f64_4x4x4f64(a, acc[s / 4][s % 4], t, 0, 0, 0);
+        }
+        v[r] = t;
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const T a = (NMF == 16 || c16 < NMF) ? s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + c16] : T(0);
+        v = M::mma(a, acc[s / 4][s % 4], v);
+      }
     }
     if constexpr (sizeof(T) == 8 && NVA == 4) {
       // DoFs 16..19 in FP64 on the 4x4x4 (four blocks) matrix-core product:
@@ -245,10 +266,13 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 // DoFs (lane group g supplies DoFs 8g..8g+7); integration: K-step ks takes
 // items 8ks..8ks+7 of every lane group.  The operands are rounded to BF16
 // (the table once at set-up, the DoF values and point values when they enter
-// a product); the point operator, accumulation and the vector-ALU tail for
-// DoFs 16.. run in FP32.  Tables in LDS: the FP32 table of Tile<float> (for
-// the tail), then the BF16 interpolation A operands [MT][16][32] and the
-// BF16 integration A operands [KSI][16][32], each lane reading 16 bytes.
+// a product); the point operator and accumulation run in FP32.  DoFs 16..
+// (4 at p = 3) are integrated by a second 16x16x32 chain on the same B
+// operands whose A rows 4j hold DoF 16 + j (the other rows are zero), so
+// that lane group j receives DoF 16 + j of its cell in accumulator element
+// 0.  Tables in LDS: the interpolation A operands [MT][16][32], the
+// integration A operands [KSI][16][32] and those of the tail DoFs, each lane
+// reading 16 bytes.
 template <int NDOF, int NQ, int C>
 struct TileBF {
   using F = Tile<float, NDOF, NQ, C>;
@@ -259,16 +283,16 @@ struct TileBF {
   static constexpr int KSI = (NS + 7) / 8;
   static constexpr int NB = 8;
   __device__ static constexpr int bdof(int g, int i) { return 8 * g + i; }
-  static constexpr int F32_BYTES = F::LDS_BYTES;
   static constexpr int A_BYTES = MT * 16 * 32 * 2;
   static constexpr int B_BYTES = KSI * 16 * 32 * 2;
-  static constexpr int LDS_BYTES = F32_BYTES + A_BYTES + B_BYTES;
+  static constexpr int LDS_BYTES = A_BYTES + (NVA > 0 ? 2 : 1) * B_BYTES;
   static_assert(NDOF <= 32, "one BF16 K-step covers at most 32 DoFs");
+  static_assert(NVA <= 4, "the tail chain places at most 4 DoFs on rows 0, 4, 8, 12");
 
   __device__ static inline void setup(unsigned char* lds, const float* __restrict__ gtab, int tid, int nt) {
-    F::setup(lds, gtab, tid, nt);
-    __bf16* ta = reinterpret_cast<__bf16*>(lds + F32_BYTES);
-    __bf16* tb = reinterpret_cast<__bf16*>(lds + F32_BYTES + A_BYTES);
+    __bf16* ta = reinterpret_cast<__bf16*>(lds);
+    __bf16* tb = reinterpret_cast<__bf16*>(lds + A_BYTES);
+    __bf16* tt = reinterpret_cast<__bf16*>(lds + A_BYTES + B_BYTES);
     for (int i = tid; i < MT * 16 * 32; i += nt) {
       const int kk = i % 32, row = (i / 32) % 16, t = i / 512;
       const int s = 4 * t + M::row_r(row), gi = M::row_g(row);
@@ -277,17 +301,23 @@ struct TileBF {
       ta[i] = (__bf16)e;
     }
     for (int i = tid; i < KSI * 16 * 32; i += nt) {
-      const int kk = i % 32, dof = (i / 32) % 16, ks = i / 512;
+      const int kk = i % 32, row = (i / 32) % 16, ks = i / 512;
       const int gk = kk / 8, s = 8 * ks + kk % 8;
-      const bool ok = s < NS && dof < NMF;
-      const float e = ok ? gtab[((gk + 4 * (s / C)) * 4 + s % C) * NDP + dof] : 0.0f;
+      const bool ok = s < NS && row < NMF;
+      const float e = ok ? gtab[((gk + 4 * (s / C)) * 4 + s % C) * NDP + row] : 0.0f;
       tb[i] = (__bf16)e;
+      if (NVA > 0) {
+        // tail DoF 16 + row / 4 on rows 0, 4, 8, 12
+        const bool okt = s < NS && row % 4 == 0 && row / 4 < NVA;
+        const float et = okt ? gtab[((gk + 4 * (s / C)) * 4 + s % C) * NDP + 16 + row / 4] : 0.0f;
+        tt[i] = (__bf16)et;
+      }
     }
   }
 
   __device__ static inline void interpolate(const unsigned char* lds, const float (&ub)[NB], int g, int c16,
                                             acc_t (&acc)[MT]) {
-    const bf8* ta = reinterpret_cast<const bf8*>(lds + F32_BYTES);
+    const bf8* ta = reinterpret_cast<const bf8*>(lds);
     bf8 b;
 #pragma unroll
     for (int i = 0; i < 8; ++i) b[i] = (__bf16)ub[i];
@@ -300,8 +330,10 @@ struct TileBF {
 
   __device__ static inline void integrate(const unsigned char* lds, const acc_t (&acc)[MT], int g, int c16, acc_t& v,
                                           float (&vv)[NVA > 0 ? NVA : 1]) {
-    const bf8* tb = reinterpret_cast<const bf8*>(lds + F32_BYTES + A_BYTES);
+    const bf8* tb = reinterpret_cast<const bf8*>(lds + A_BYTES);
+    const bf8* tt = reinterpret_cast<const bf8*>(lds + A_BYTES + B_BYTES);
     v = acc_t{0, 0, 0, 0};
+    acc_t vt = acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KSI; ++ks) {
       bf8 b;
@@ -312,22 +344,13 @@ struct TileBF {
       }
       const bf8 a = tb[(ks * 16 + c16) * 4 + g];
       v = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, v, 0, 0, 0);
-    }
-    if (NVA > 0) {
-      const float* s_tab = reinterpret_cast<const float*>(lds);
-      float part[NVA > 0 ? NVA : 1];
-#pragma unroll
-      for (int jj = 0; jj < NVA; ++jj) part[jj] = 0.0f;
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const float x = acc[s / 4][s % 4];
-        const float* e = s_tab + ((g + 4 * (s / C)) * C + s % C) * NDP + 16;
-#pragma unroll
-        for (int jj = 0; jj < NVA; ++jj) part[jj] += e[jj] * x;
+      if (NVA > 0) {
+        const bf8 at = tt[(ks * 16 + c16) * 4 + g];
+        vt = __builtin_amdgcn_mfma_f32_16x16x32_bf16(at, b, vt, 0, 0, 0);
       }
-#pragma unroll
-      for (int jj = 0; jj < NVA; ++jj) vv[jj] = sum_rows(part[jj]);
     }
+#pragma unroll
+    for (int jj = 0; jj < (NVA > 0 ? NVA : 1); ++jj) vv[jj] = vt[0];
   }
 };
 
@@ -460,9 +483,19 @@ __device__ inline void point_geo(const T* __restrict__ geo, int ncp, const T* __
 // stored component by component; each block stages its local indices once
 // and runs stage / tiles / reduce per component (the LDS holds one
 // component at a time), re-reading the cell data from cache.
+// Register budget: four waves per SIMD (two workgroups per CU, the LDS
+// limit of the forward kernels).  The FP64 backward at P3 stages u and g
+// (about 90 KB of LDS per workgroup at the 64^3 x 6 mesh), so one workgroup
+// fits per CU and two waves per SIMD lose nothing; the budget then allows 256
+// registers instead of spilling at 128.
+template <typename T, int NDOF, int MODE>
+struct MinWaves {
+  static constexpr int value = (sizeof(T) == 8 && NDOF == 20 && MODE == MODE_BACKWARD) ? 2 : 4;
+};
+
 template <typename T, int NDOF, int NQ, int C, int MODE, bool BF, bool CURV, int NCOMP>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
-cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* __restrict__ kappa,
+__global__ void __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE>::value, 8))) cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* __restrict__ kappa,
           T* __restrict__ out, T* __restrict__ dk) {
   using TL = typename EngineSel<T, NDOF, NQ, C, BF>::type;
   using M = Mfma<T>;
@@ -582,19 +615,14 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
           // loaded with the per-point geometry
         } else if (kappa) {
           const int cc = valid ? cell : nc - 1;
-          const uint32_t kof = ((uint32_t)g * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T);
+          // row base 4k and a lane row below 4 (the lane's point in a full
+          // group, clamped in a partly used last one): the 32-bit offset
+          // stays below 4 nc sizeof(T)
 #pragma unroll
-          for (int k = 0; k < KP; ++k) {
-            if (4 * k + 3 < NQ) {
-              kq[k] = load_at(kappa + (long)(4 * k) * nc, kof);
-            } else {
-              // partly used last group: row base 4k, lane row q - 4k < 4, so
-              // the 32-bit offset stays below 4 nc sizeof(T), as in the full groups
-              const int q = min(g + 4 * k, NQ - 1);
-              kq[k] = load_at(kappa + (long)(4 * k) * nc,
-                              ((uint32_t)(q - 4 * k) * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T));
-            }
-          }
+          for (int k = 0; k < KP; ++k)
+            kq[k] = load_at(kappa + (long)(4 * k) * nc,
+                            ((uint32_t)lanes::kappa_lane_row(NQ, g, k) * (uint32_t)nc + (uint32_t)cc) *
+                                (uint32_t)sizeof(T));
         } else {
 #pragma unroll
           for (int k = 0; k < KP; ++k) kq[k] = T(1);
@@ -606,20 +634,26 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
 #pragma unroll
           // rows beyond the cell's DoFs (fewer than 16 at p <= 2) have no slot
           for (int r = 0; r < 4; ++r)
-            pv[r] = (TL::NMF == 16 || M::row(g, r) < TL::NMF) ? load_at(d.pos + (long)M::row(0, r) * ncp, pof)
+            pv[r] = lanes::pos_row(sizeof(T), NDOF, g, r) >= 0 ? load_at(d.pos + (long)M::row(0, r) * ncp, pof)
                                                                : uint16_t(0);
           if (TL::NVA > 0)
             pv[4] = load_at(d.pos + 16 * (long)ncp,
-                            ((uint32_t)min(g, TL::NVA - 1) * (uint32_t)ncp + (uint32_t)cell) * 2u);
+                            ((uint32_t)(lanes::pos_tail_row(NDOF, g) - 16) * (uint32_t)ncp + (uint32_t)cell) * 2u);
         }
         T ub[NB];
         T gb[BWD ? NB : 1];
 #pragma unroll
         for (int ks = 0; ks < NB; ++ks) {
+          // operand rows beyond the cell's DoFs read a valid row and are
+          // zeroed afterwards (no branch around the loads)
           const int j = TL::bdof(g, ks);
-          const int l = j < NDOF ? s_lidx[j * kBlockCells + cl] : 0;
-          ub[ks] = j < NDOF ? s_u[l] : T(0);
-          if (BWD) gb[BWD ? ks : 0] = j < NDOF ? s_u[d.nbd_max + l] : T(0);
+          const int l = s_lidx[lanes::operand_row(NDOF, j) * kBlockCells + cl];
+          const T x = s_u[l];
+          ub[ks] = j < NDOF ? x : T(0);
+          if (BWD) {
+            const T y = s_u[d.nbd_max + l];
+            gb[BWD ? ks : 0] = j < NDOF ? y : T(0);
+          }
         }
         acc_t acc[MT];
         // matrix-core section of the tile at raised wave priority: the
@@ -699,7 +733,7 @@ cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* 
           if (valid) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (TL::NMF == 16 || M::row(g, r) < TL::NMF) s_slot[pv[r]] = v[r];
+              if (lanes::pos_row(sizeof(T), NDOF, g, r) >= 0) s_slot[pv[r]] = v[r];
             if (TL::NVA > 0 && g < TL::NVA) {
               T mine = vv[0];
 #pragma unroll
@@ -852,10 +886,9 @@ hipError_t launch_cg_mf(const CGDev& d, const void* u, const void* g, const void
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
-  // With ev: ev[0] is a marker recorded after the preceding work on the
-  // stream has finished, ev[1] takes the end timestamp of this dispatch.
-  if (ev) (void)hipEventRecord(ev[0], s);
-  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, nullptr, ev ? ev[1] : nullptr, 0u, d,
+  // With ev: the start and end timestamps of this dispatch (no separate
+  // marker packet, so back-to-back launches stay back to back).
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
                         (const T*)u, (const T*)g, (const T*)kappa, (T*)out, (T*)dk);
   e = hipGetLastError();
   if (e != hipSuccess || out == nullptr) return e;
@@ -870,8 +903,7 @@ hipError_t launch_cg_vec(const CGDev& d, const void* kappa, void* out, hipStream
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, d.n_blocks);
-  if (ev) (void)hipEventRecord(ev[0], s);
-  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, nullptr, ev ? ev[1] : nullptr, 0u, d,
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
                         (const T*)kappa, (T*)out);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -988,7 +1020,8 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
     for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
   }
   __syncthreads();
-  const int wave = threadIdx.x >> 6;
+  // the wave index is uniform in the wave: scalar registers for the tile loop
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ncp = d.ncp, nc = d.n_cell, nf = d.n_face;
   const T* geo = static_cast<const T*>(d.geo);
   const T* fgeo = static_cast<const T*>(d.fgeo);
@@ -1012,20 +1045,29 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
     // ---- cell term
     {
       T ub[TC::KS];
+      // the tile's DoF values from a uniform row base (cell0) and a 32-bit
+      // lane offset below 16 NDOF sizeof(T), read at a valid cell and masked
+      const T* ut = u + (long)cell0 * NDOF;
 #pragma unroll
       for (int s = 0; s < TC::KS; ++s) {
         const int j = 4 * s + g;
-        ub[s] = (valid && j < NDOF) ? u[(long)cell * NDOF + j] : T(0);
+        const T x = load_at(ut, (uint32_t)((cc - cell0) * NDOF + (j < NDOF ? j : NDOF - 1)) * (uint32_t)sizeof(T));
+        ub[s] = (valid && j < NDOF) ? x : T(0);
       }
-      const T G0 = geo[0 * ncp + cell], G1 = geo[1 * ncp + cell], G2 = geo[2 * ncp + cell];
-      const T G3 = geo[3 * ncp + cell], G4 = geo[4 * ncp + cell], G5 = geo[5 * ncp + cell];
-      const T adet = (C == 4) ? geo[6 * ncp + cell] : T(0);
+      // cell data: uniform row bases and 32-bit lane offsets (below 4 ncp
+      // sizeof(T), within the set-up's 32-bit limit)
+      const uint32_t coff = (uint32_t)cell * (uint32_t)sizeof(T);
+      const T G0 = load_at(geo, coff), G1 = load_at(geo + (long)ncp, coff), G2 = load_at(geo + 2 * (long)ncp, coff);
+      const T G3 = load_at(geo + 3 * (long)ncp, coff), G4 = load_at(geo + 4 * (long)ncp, coff);
+      const T G5 = load_at(geo + 5 * (long)ncp, coff);
+      const T adet = (C == 4) ? load_at(geo + 6 * (long)ncp, coff) : T(0);
       T kq[TC::KP];
 #pragma unroll
-      for (int k = 0; k < TC::KP; ++k) {
-        const int q = g + 4 * k;
-        kq[k] = kc ? kc[(long)(q < NQ ? q : NQ - 1) * nc + cc] : T(1);
-      }
+      for (int k = 0; k < TC::KP; ++k)
+        kq[k] = kc ? load_at(kc + (long)(4 * k) * nc,
+                             ((uint32_t)lanes::kappa_lane_row(NQ, g, k) * (uint32_t)nc + (uint32_t)cc) *
+                                 (uint32_t)sizeof(T))
+                   : T(1);
       acc_t acc[TC::MT];
       __builtin_amdgcn_s_setprio(1);  // matrix-core section at raised wave priority
       TC::interpolate(s_tab, ub, g, c16, acc);
@@ -1175,7 +1217,8 @@ dg_grad_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ gv, T* __
     for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
   }
   __syncthreads();
-  const int wave = threadIdx.x >> 6;
+  // the wave index is uniform in the wave: scalar registers for the tile loop
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ncp = d.ncp, nc = d.n_cell, nf = d.n_face;
   const T* geo = static_cast<const T*>(d.geo);
   const T* fgeo = static_cast<const T*>(d.fgeo);
@@ -1296,8 +1339,7 @@ hipError_t launch_dg_t(const DGDev& d, const void* u, const void* kc, const void
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int grid = persistent_grid((const void*)kern, lds, (ntiles + kWaves - 1) / kWaves);
-  if (ev) (void)hipEventRecord(ev[0], s);
-  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, nullptr, ev ? ev[1] : nullptr, 0u, d,
+  hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, s, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr, 0u, d,
                         (const T*)u, (const T*)kc, (const T*)kf, (T*)v);
   e = hipGetLastError();
   return e;

@@ -10,6 +10,7 @@
 // described where it is built.
 #include "../../include/tetmf.h"
 #include "internal.h"
+#include "lane_map.h"
 
 #include <algorithm>
 #include <array>
@@ -447,6 +448,50 @@ uint64_t spread21(uint64_t x) {
 // Locality order of the cells (Sec. 2.5 motivates it; the method here is a
 // space-filling curve rather than the paper's greedy grouping): sort by the
 // Morton key of the centroid, ties by user id.
+// Every per-lane read of the CG cell kernel instantiation that serves an
+// operator, enumerated from the index maps the kernel itself uses
+// (lane_map.h): each row inside its array, the split of a slot row into the
+// uniform row base and the lane part that the kernel's loads rely on, and
+// every 32-bit byte offset below 2^32 at ncp_max cells, the largest count the
+// set-up accepts at this degree.  Throws DEVICE naming the failing map.
+void check_lane_maps(int esize, int nd, int nq, int64_t ncp_max) {
+  auto bad = [&](const std::string& what) {
+    throw Error(TETMF_ERR_DEVICE, "kernel lane map (n_dof_cell " + std::to_string(nd) + ", n_q " +
+                                      std::to_string(nq) + "): " + what);
+  };
+  const uint64_t lim = (uint64_t)1 << 32, n = (uint64_t)ncp_max;
+  for (int g = 0; g < 4; ++g) {
+    for (int r = 0; r < 4; ++r) {
+      const int pr = lanes::pos_row(esize, nd, g, r);
+      if (pr < -1 || pr >= nd) bad("slot-position row " + std::to_string(pr) + " outside the cell's DoFs");
+      if (pr >= 0 && lanes::acc_row(esize, g, 0) + lanes::acc_row(esize, 0, r) != pr)
+        bad("slot-position row is not row base + lane part");
+      if (pr >= 0 && ((uint64_t)lanes::acc_row(esize, g, 0) * n + n - 1) * 2 >= lim)
+        bad("slot-position offset beyond 32 bits");
+    }
+    const int tr = lanes::pos_tail_row(nd, g);
+    if (lanes::n_tail(nd) > 0) {
+      if (tr < 16 || tr >= nd) bad("tail slot-position row outside the cell's DoFs");
+      if (((uint64_t)(tr - 16) * n + n - 1) * 2 >= lim) bad("tail slot-position offset beyond 32 bits");
+    } else if (tr != -1) {
+      bad("tail slot-position row without tail DoFs");
+    }
+    for (int k = 0; k < (nq + 3) / 4; ++k) {
+      const int lr = lanes::kappa_lane_row(nq, g, k);
+      if (lr < 0 || lr > 3 || 4 * k + lr >= nq) bad("coefficient row outside the rule");
+      if (((uint64_t)lr * n + n - 1) * esize >= lim) bad("coefficient offset beyond 32 bits");
+    }
+  }
+  for (int j = 0; j < 32; ++j) {
+    const int o = lanes::operand_row(nd, j);
+    if (o < 0 || o >= nd) bad("operand row outside the cell's DoFs");
+  }
+  // geometry (cell * size, curved: point row below 4 from a row base) and
+  // the block-index staging (2 (j ncp + cell in block))
+  if ((4 * n - 1) * esize >= lim) bad("geometry offset beyond 32 bits");
+  if (2 * ((uint64_t)(nd - 1) * n + 255) >= lim) bad("index staging offset beyond 32 bits");
+}
+
 std::vector<int32_t> locality_order(const tetmf_mesh& m) {
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t v = 0; v < m.nv; ++v)
@@ -710,6 +755,7 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
   if (op->ncp > max_cells)
     throw Error(TETMF_ERR_UNSUPPORTED, "mesh too large for one operator: at most " + std::to_string(max_cells) +
                                            " cells at this degree (32-bit indexing)");
+  check_lane_maps((int)op->esize(), nd, op->nq, max_cells);
   std::vector<int32_t> bmin(ntmp, INT32_MAX), bmax(ntmp, -1);
   for (int64_t i = 0; i < nc; ++i) {
     int32_t b = (int32_t)(i / kBlockCells);

@@ -162,3 +162,21 @@ def test_vector_setup_checks():
     fp, fw = synth.tri_rule(4)
     assert (tm.check_setup(mesh, 2, (qp, qw), kind="dg", frule=(fp, fw), n_components=3) ==
             tm.check_setup(mesh, 2, (qp, qw), kind="dg", frule=(fp, fw)))
+
+
+# every compiled CG cell-kernel shape: (degree, cell rule degree)
+KERNEL_SHAPES = [(1, 2), (2, 2), (2, 4), (3, 4), (3, 6)]
+
+
+@pytest.mark.parametrize("degree,qdeg", KERNEL_SHAPES)
+@pytest.mark.parametrize("precision", ["f64", "f32", "bf16in"])
+@pytest.mark.parametrize("sigma", [0.0, 1.0])
+def test_kernel_lane_maps_every_instantiation(L, degree, qdeg, precision, sigma):
+    """The set-up enumerates every lane's reads of the cell kernel it will
+    launch (slot positions, tail slots, coefficient rows, operand rows) from
+    the maps the kernel uses, and checks rows and 32-bit offsets at the
+    largest accepted mesh: a read past the cell's DoFs (such as the slot
+    rows beyond 10 DoFs at P2 or 4 at P1) fails here, on the CPU."""
+    xyz, tets = synth.kuhn_cube_mesh(2, 0.15)
+    nd, nf = L.check_setup(L.Mesh(xyz, tets), degree, synth.tet_rule(qdeg), precision=precision, sigma=sigma)
+    assert nd == (degree * 2 + 1) ** 3
