@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from tests.tetmf_cases import cg_map, rel_err
+from tests.tetmf_cases import cg_map, rel_err, row_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -55,6 +55,7 @@ def test_cg_apply_variable_kappa(p, qdeg, n, precision):
     y = c["A"] @ u
     v = run_apply(c, u)
     assert rel_err(v, y[c["idx"]]) <= TOL[precision]
+    assert row_err(v, c["A"], u, c["idx"]) <= TOL[precision]
 
 
 def test_cg_reduced_rule_unit_kappa():
@@ -73,6 +74,7 @@ def test_cg_reduced_rule_unit_kappa():
     u = synth.uniform(0, synth.STREAM_U, A.shape[0])
     v = op.apply(torch.from_numpy(u[idx]).cuda()).cpu().numpy()
     assert rel_err(v, (A @ u)[idx]) <= 1e-12
+    assert row_err(v, A, u, idx) <= 1e-12
 
 
 def test_cg_c1_config():
@@ -82,6 +84,7 @@ def test_cg_c1_config():
     v = run_apply(c, u)
     y = c["A"] @ u
     assert rel_err(v, y[c["idx"]]) <= 1e-12
+    assert row_err(v, c["A"], u, c["idx"]) <= 1e-12
     assert c["op"].n_dofs == 17 ** 3
 
 
@@ -92,6 +95,7 @@ def test_cg_helmholtz_dirichlet(precision):
     v = run_apply(c, u)
     y = c["A"] @ u
     assert rel_err(v, y[c["idx"]]) <= TOL[precision]
+    assert row_err(v, c["A"], u, c["idx"]) <= TOL[precision]
     # constrained rows are the identity
     cons = c["d"]["constrained"][c["idx"]]
     assert np.array_equal(v[cons], u[c["idx"]][cons].astype(v.dtype)) if precision == "f64" else True
@@ -104,6 +108,7 @@ def test_cg_orderings(shuffle, ordering):
     u = synth.uniform(0, synth.STREAM_U, c["A"].shape[0])
     v = run_apply(c, u)
     assert rel_err(v, (c["A"] @ u)[c["idx"]]) <= 1e-12
+    assert row_err(v, c["A"], u, c["idx"]) <= 1e-12
 
 
 def test_cg_deterministic():
@@ -155,6 +160,7 @@ def test_cg_backward_vs_oracle():
     gt = torch.from_numpy(g[c["idx"]]).to(c["dev"])
     du, dk = op.backward(ut, gt, c["kl"])
     assert rel_err(du.cpu().numpy(), (c["A"].T @ g)[c["idx"]]) <= 1e-12
+    assert row_err(du.cpu().numpy(), c["A"].T.tocsr(), g, c["idx"]) <= 1e-12
     dko = oracle.cg_kappa_grad(c["xyz"], c["tets"], 2, c["qp"], c["qw"], u, g, dofs=c["d"])
     dku = op.cell_data_to_user(dk).cpu().numpy()
     assert rel_err(dku, dko) <= 1e-12

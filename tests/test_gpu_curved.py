@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from tests.tetmf_cases import cg_map, rel_err
+from tests.tetmf_cases import cg_map, rel_err, row_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -40,6 +40,7 @@ def test_curved_apply(p, qdeg, n, precision):
     ut = torch.from_numpy(u[c["idx"]]).to(c["dev"], c["op"].dtype)
     v = c["op"].apply(ut, c["kl"]).double().cpu().numpy()
     assert rel_err(v, (c["A"] @ u)[c["idx"]]) <= TOL[precision]
+    assert row_err(v, c["A"], u, c["idx"]) <= TOL[precision]
 
 
 @pytest.mark.parametrize("p,qdeg", [(2, 4), (3, 6)])
@@ -48,6 +49,7 @@ def test_curved_helmholtz_dirichlet(p, qdeg):
     u = synth.uniform(1, synth.STREAM_U, c["A"].shape[0])
     v = c["op"].apply(torch.from_numpy(u[c["idx"]]).to(c["dev"]), c["kl"]).cpu().numpy()
     assert rel_err(v, (c["A"] @ u)[c["idx"]]) <= 1e-12
+    assert row_err(v, c["A"], u, c["idx"]) <= 1e-12
 
 
 def test_curved_coordinate_field_energy():

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from tests.tetmf_cases import dg_map, rel_err
+from tests.tetmf_cases import dg_map, rel_err, row_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -39,6 +39,7 @@ def test_dg_apply(p, bc):
     y = c["A"] @ u
     v = c["op"].apply(torch.from_numpy(u[c["idx"]]).to(c["dev"]), c["klc"], c["klf"]).cpu().numpy()
     assert rel_err(v, y[c["idx"]]) <= 1e-12
+    assert row_err(v, c["A"], u, c["idx"]) <= 1e-12
 
 
 def test_dg_apply_f32_shuffled_unit_kappa():
@@ -47,6 +48,7 @@ def test_dg_apply_f32_shuffled_unit_kappa():
     y = c["A"] @ u
     v = c["op"].apply(torch.from_numpy(u[c["idx"]]).to(c["dev"], torch.float32)).double().cpu().numpy()
     assert rel_err(v, y[c["idx"]]) <= 1e-5
+    assert row_err(v, c["A"], u, c["idx"]) <= 1e-5
 
 
 def test_dg_mass_and_determinism():
@@ -57,6 +59,7 @@ def test_dg_mass_and_determinism():
     v2 = c["op"].apply(ut, c["klc"], c["klf"])
     assert torch.equal(v1, v2)
     assert rel_err(v1.cpu().numpy(), (c["A"] @ u)[c["idx"]]) <= 1e-12
+    assert row_err(v1.cpu().numpy(), c["A"], u, c["idx"]) <= 1e-12
 
 
 @pytest.mark.parametrize("p,bc,precision", [(1, "dirichlet", "f64"), (2, "neumann", "f64"), (3, "dirichlet", "f64"),
@@ -74,6 +77,7 @@ def test_dg_backward_vs_oracle(p, bc, precision):
     du, dk, dkf = op.backward(ut, gt, c["klc"], kappa_face=c["klf"], need_dkappa_face=True)
     tol = 1e-12 if precision == "f64" else 1e-5
     assert rel_err(du.double().cpu().numpy(), (c["A"].T @ g)[idx]) <= tol
+    assert row_err(du.double().cpu().numpy(), c["A"].T.tocsr(), g, idx) <= tol
     xyz, tets = c["mesh"]
     qp, qw, fp, fw = c["rules"]
     dkc_o, dkf_o = oracle.dg_kappa_grad(xyz, tets, p, qp, qw, fp, fw, u, g, bc=bc)
@@ -157,6 +161,7 @@ def test_dg_vector_field():
     gt = torch.from_numpy(g[idx3]).cuda()
     v = op.apply(ut, klc, klf).cpu().numpy()
     assert rel_err(v, (Av @ u)[idx3]) <= 1e-12
+    assert row_err(v, Av, u, idx3) <= 1e-12
     du, dk, dkf = op.backward(ut, gt, klc, kappa_face=klf, need_dkappa_face=True)
     assert rel_err(du.cpu().numpy(), (Av.T @ g)[idx3]) <= 1e-12
     parts = [oracle.dg_kappa_grad(xyz, tets, 2, qp, qw, fp, fw, u[c * n:(c + 1) * n], g[c * n:(c + 1) * n],

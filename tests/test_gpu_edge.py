@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from tests.tetmf_cases import cg_map, dg_map, rel_err
+from tests.tetmf_cases import cg_map, dg_map, rel_err, row_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -33,7 +33,9 @@ def _cg_check(xyz, tets, p, h, bc="neumann", sigma=0.0, precision="f64", curved=
     if precision != "f64":
         u = u.astype(np.float32).astype(np.float64)
     v = op.apply(torch.from_numpy(u[idx]).to("cuda", op.dtype), kl).double().cpu().numpy()
-    return rel_err(v, (A @ u)[idx])
+    # the larger of the vector-norm error and the entry-wise error against
+    # each row's scale sum_j |a_ij| |u_j|
+    return max(rel_err(v, (A @ u)[idx]), row_err(v, A, u, idx))
 
 
 @pytest.mark.parametrize("p", [1, 2, 3])
@@ -81,6 +83,7 @@ def test_dg_small(mesh):
     u = synth.uniform(0, synth.STREAM_U, A.shape[0])
     v = op.apply(torch.from_numpy(u[idx]).cuda(), klc, klf).cpu().numpy()
     assert rel_err(v, (A @ u)[idx]) <= 1e-12
+    assert row_err(v, A, u, idx) <= 1e-12
 
 
 @pytest.mark.parametrize("mesh", ["one_tet", "ragged"])

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import synth
-from tests.tetmf_cases import cg_map, rel_err
+from tests.tetmf_cases import cg_map, rel_err, row_err
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -42,6 +42,7 @@ def test_vector_apply(p, qdeg, n, precision):
     ut = torch.from_numpy(u[c["idx3"]]).to(c["dev"], c["op"].dtype)
     v = c["op"].apply(ut, c["kl"]).double().cpu().numpy()
     assert rel_err(v, (c["Av"] @ u)[c["idx3"]]) <= TOL[precision]
+    assert row_err(v, c["Av"], u, c["idx3"]) <= TOL[precision]
 
 
 @pytest.mark.parametrize("curved", [False, True])
@@ -50,6 +51,7 @@ def test_vector_helmholtz_dirichlet(curved):
     u = synth.uniform(1, synth.STREAM_U, c["Av"].shape[0])
     v = c["op"].apply(torch.from_numpy(u[c["idx3"]]).to(c["dev"]), c["kl"]).cpu().numpy()
     assert rel_err(v, (c["Av"] @ u)[c["idx3"]]) <= 1e-12
+    assert row_err(v, c["Av"], u, c["idx3"]) <= 1e-12
 
 
 def test_vector_coordinate_field_energy():
