@@ -11,13 +11,19 @@ jittered by up to 0.15 h (seed 0), symmetric 24-point degree-6 cell rule,
 random input vector.  ``value`` is the FP64 apply; the FP32 (matrix-core
 f32) and BF16-operand applies on the same inputs are reported beside it.
 
-Timing: the apply (cell kernel + combine) is captured in a HIP graph and
-replayed; ``ms_per_step`` is the mean over the `steps` timed replays
-bracketed by device synchronisations, and ``step_ms`` gives the median and
-10th/90th percentiles of single replays (HIP events, at least 50).  The
-roofline object refers to the dominant kernel (the cell kernel): algorithmic
-flops (or bytes) per launch divided by the MEDIAN of its launch durations,
-measured with a HIP event pair around each launch on the stream it runs on.
+Timing: each measurement starts after about 1 s of untimed calls (the GPU
+leaves its idle clock state; the first launches after host-side set-up run
+slower), and every timed loop runs its calls back to back (an event or a
+host gap between calls measurably slows the next ones for tens of calls).
+The apply (cell kernel + combine) is captured in a HIP graph and replayed;
+``ms_per_step`` is the mean over the `steps` timed replays (after `warmup`
+untimed ones) bracketed by device synchronisations, and ``step_ms`` gives
+the median and 10th/90th percentiles over 10 further such loops.  The
+roofline object refers to the dominant kernel (the cell kernel):
+algorithmic flops (or bytes) per launch divided by the MEDIAN of its launch
+durations, from the start and end timestamps of each dispatch (HIP events
+attached to the launch on the stream it runs on) over at least 50
+consecutive launches.
 ``traffic`` is the HBM byte count per launch from rocprofv3 FETCH_SIZE +
 WRITE_SIZE counters scaled by a copy-kernel calibration (profiles/), or null
 when the kernel source changed since the counters were taken.
@@ -104,6 +110,22 @@ def rand_vec(n, dtype, seed=2):
     import torch
     g = torch.Generator(device="cpu").manual_seed(seed)
     return (torch.rand(n, generator=g, dtype=torch.float64) * 2 - 1).to("cuda", dtype)
+
+
+SETTLE_S = 1.0
+
+
+def settle(fn, seconds=None):
+    """Untimed calls for about `seconds`: the GPU leaves its idle clock state
+    (after host-side set-up the first launches run measurably slower), so the
+    timed loops see the steady state a solver sees."""
+    import torch
+    seconds = SETTLE_S if seconds is None else seconds
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
 
 
 def loop_ms(fn, steps, warmup):
@@ -215,10 +237,29 @@ def graph_of(fn, ref, out):
         return None
 
 
+def loop_stats(fn, steps, reps=10):
+    """Mean ms per call of `reps` back-to-back loops of `steps` calls, each
+    bracketed by a HIP event pair (no event between the calls of a loop)."""
+    import torch
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        b.synchronize()
+        out.append(a.elapsed_time(b) / steps)
+    return out
+
+
 def measure_apply(op, kl, u, steps, warmup, prec, traffic_key=None, kf=None, graph=True, cold=False):
-    """Apply throughput of an op: mean over `steps` (graph replays when the
-    capture reproduces the eager result), single-step statistics, kernel
-    statistics and the roofline at the median kernel time."""
+    """Apply throughput of an op, every timed loop back to back after a
+    settle phase: kernel statistics from the dispatch timestamps of
+    max(steps, 50) consecutive launches (median used for the roofline), the
+    eager loop, then (when the capture reproduces the eager result bitwise) a
+    HIP graph of one apply, replayed: 10 loops of `steps` replays for the
+    step statistics and one loop of `steps` for ms_per_step."""
     import torch
     out = torch.empty(op.n_vec, dtype=op.dtype, device="cuda")
 
@@ -228,12 +269,14 @@ def measure_apply(op, kl, u, steps, warmup, prec, traffic_key=None, kf=None, gra
     torch.cuda.synchronize()
     ref = out.clone()
     nstat = max(steps, STAT_SAMPLES)
+    settle(call)
+    kt = stats(kernel_ms(op, call, nstat))
     ms_eager = loop_ms(call, steps, warmup)
     g = graph_of(call, ref, out) if graph else None
     step_fn = g.replay if g is not None else call
-    ms_step = loop_ms(step_fn, steps, warmup) if g is not None else ms_eager
-    step = stats(per_call_ms(step_fn, nstat))
-    kt = stats(kernel_ms(op, call, nstat))
+    settle(step_fn)
+    step = stats(loop_stats(step_fn, steps))
+    ms_step = loop_ms(step_fn, steps, warmup)
     r = {"value": round(op.n_vec / (ms_step * 1e-3), 1), "ms_per_step": round(ms_step, 5),
          "ms_per_step_eager": round(ms_eager, 5), "timing": "graph" if g is not None else "eager",
          "step_ms": step, "kernel_ms": kt, "roofline": roofline(op, prec, kt["median"], traffic_key)}
@@ -386,8 +429,9 @@ def run_c2(args):
 
     def bwd():
         op.backward(u, g, klc, kappa_face=klf, need_dkappa_face=True)
+    settle(bwd)
+    bs = stats(loop_stats(bwd, args.steps))
     ms_b = loop_ms(bwd, args.steps, args.warmup)
-    bs = stats(per_call_ms(bwd, max(args.steps, STAT_SAMPLES)))
     r["backward"] = {"what": "du = A g, dkappa_cell, dkappa_face", "ms_per_step": round(ms_b, 5), "step_ms": bs,
                      "roofline": roofline(op, "f64", bs["median"], backward=True)}
     r["workload"] = (f"DG SIPG P3, {n}^3x6 Kuhn tets ({op.n_cell} cells, {op.n_dofs} DoFs), lognormal(0,0.5) cell "
@@ -412,8 +456,9 @@ def run_c4(args):
 
     def bwd():
         op.backward(u, g, kl)
-    ms_b = loop_ms(bwd, args.steps, args.warmup)
+    settle(bwd)
     kb = stats(kernel_ms(op, bwd, max(args.steps, STAT_SAMPLES)))
+    ms_b = loop_ms(bwd, args.steps, args.warmup)
     r["backward"] = {"what": "du = A g and dkappa per point", "ms_per_step": round(ms_b, 5), "kernel_ms": kb,
                      "roofline": roofline(op, "f64", kb["median"], backward=True),
                      "cold_step_ms": stats(per_call_ms(bwd, 20, cold=True))}
@@ -485,6 +530,7 @@ def run_f2(args, scalar=None):
     def three():
         for c in range(3):
             ops.apply(u[c * n:(c + 1) * n], kl, out=outs[c])
+    settle(three)
     ms_three = loop_ms(three, args.steps, args.warmup)
     r["ms_three_scalar_applies"] = round(ms_three, 5)
     r["speedup_vs_three_scalar"] = round(ms_three / r["ms_per_step_eager"], 3)
@@ -539,8 +585,9 @@ def run_f4(args, solve_ctx=None):
 
     def smooth():
         op.chebyshev(b, inv, 5, lmax / 15.0, lmax, x=x)
+    settle(smooth)
+    st = stats(loop_stats(smooth, args.steps))
     ms = loop_ms(smooth, args.steps, args.warmup)
-    st = stats(per_call_ms(smooth, max(args.steps, STAT_SAMPLES) // 2))
     return {"ms_per_smoothing": round(ms, 5), "smoothing_ms": st, "steps": 5, "ms_per_step": round(ms / 5, 5),
             "DoFs_per_s_per_step": round(op.n_dofs * 5 / (ms * 1e-3), 1), "lambda_max_estimate": lam,
             "estimate_seconds_20_steps": round(t_est, 4),
@@ -590,6 +637,7 @@ def copy_calibration(mib=1024, reps=3):
 
 
 def main():
+    global SETTLE_S
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -599,9 +647,12 @@ def main():
     ap.add_argument("--config", default="all", choices=("all", "c3") + CONFIGS,
                     help="all (default): the headline line with every other workload inside it; c3: the "
                          "headline alone; c2 ... order: one workload, printed as its own JSON line")
+    ap.add_argument("--settle", type=float, default=SETTLE_S,
+                    help="seconds of untimed calls before each measurement (0 under a counter profiler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
     args = ap.parse_args()
+    SETTLE_S = args.settle
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the operator shards by "
               "cell partition with one halo exchange per apply, which this build does not run).", file=sys.stderr)
