@@ -271,6 +271,7 @@ def measure_apply(op, kl, u, steps, warmup, prec, traffic_key=None, kf=None, gra
     nstat = max(steps, STAT_SAMPLES)
     settle(call)
     kt = stats(kernel_ms(op, call, nstat))
+    settle(call)
     ms_eager = loop_ms(call, steps, warmup)
     g = graph_of(call, ref, out) if graph else None
     step_fn = g.replay if g is not None else call

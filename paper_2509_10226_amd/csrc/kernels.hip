@@ -627,19 +627,26 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE>::value, 8))) cg_kerne
 #pragma unroll
           for (int k = 0; k < KP; ++k) kq[k] = T(1);
         }
+        // LDS slots of the lane's result rows; straight cells request them
+        // with the cell data, curved FP64 cells after the point loop (they are
+        // needed only for the slot writes, and the per-point geometry needs
+        // the registers before that: 622 -> 590 us at 64^3 x 6; FP32 has the
+        // registers and keeps the early request)
+        constexpr bool kLateSlots = CURV && sizeof(T) == 8;
         uint16_t pv[4 + TL::NVA];
-        if (write_out) {
+        auto load_slots = [&]() {
           // row(g, r) = row(g, 0) + row(0, r): lane part and uniform part
           const uint32_t pof = ((uint32_t)M::row(g, 0) * (uint32_t)ncp + (uint32_t)cell) * 2u;
-#pragma unroll
           // rows beyond the cell's DoFs (fewer than 16 at p <= 2) have no slot
+#pragma unroll
           for (int r = 0; r < 4; ++r)
             pv[r] = lanes::pos_row(sizeof(T), NDOF, g, r) >= 0 ? load_at(d.pos + (long)M::row(0, r) * ncp, pof)
                                                                : uint16_t(0);
-          if (TL::NVA > 0)
+          if constexpr (TL::NVA > 0)
             pv[4] = load_at(d.pos + 16 * (long)ncp,
                             ((uint32_t)(lanes::pos_tail_row(NDOF, g) - 16) * (uint32_t)ncp + (uint32_t)cell) * 2u);
-        }
+        };
+        if (!kLateSlots && write_out) load_slots();
         T ub[NB];
         T gb[BWD ? NB : 1];
 #pragma unroll
@@ -727,6 +734,7 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE>::value, 8))) cg_kerne
           if constexpr (C == 4) acc[(i0 + 3) / 4][(i0 + 3) % 4] = qok ? sigma * w * adet * val : T(0);
         }
         if (write_out) {
+          if (kLateSlots) load_slots();
           acc_t v;
           T vv[TL::NVA > 0 ? TL::NVA : 1];
           TL::integrate(s_eng, acc, g, c16, v, vv);
@@ -734,11 +742,11 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE>::value, 8))) cg_kerne
 #pragma unroll
             for (int r = 0; r < 4; ++r)
               if (lanes::pos_row(sizeof(T), NDOF, g, r) >= 0) s_slot[pv[r]] = v[r];
-            if (TL::NVA > 0 && g < TL::NVA) {
+            if constexpr (TL::NVA > 0) {
               T mine = vv[0];
 #pragma unroll
               for (int jj = 1; jj < (TL::NVA > 0 ? TL::NVA : 1); ++jj) mine = (g == jj) ? vv[jj] : mine;
-              s_slot[pv[4]] = mine;
+              if (g < TL::NVA) s_slot[pv[4]] = mine;
             }
           }
         }

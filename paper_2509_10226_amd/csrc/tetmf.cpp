@@ -856,8 +856,11 @@ void setup_cg(tetmf_op* op, const tetmf_mesh& m, bool device) {
           others.push_back((int32_t)g);
         }
       }
-    // the block's other DoFs, likewise ordered by their number of slots here
-    std::stable_sort(others.begin(), others.end(), [&](int32_t a, int32_t c) { return occ[a] > occ[c]; });
+    // the block's other DoFs, likewise ordered by their number of slots here,
+    // and by global id among equal counts: the partial sums of a block are
+    // then written at increasing addresses within each count class
+    std::sort(others.begin(), others.end(),
+              [&](int32_t a, int32_t c) { return occ[a] > occ[c] || (occ[a] == occ[c] && a < c); });
     for (int32_t g : others) local_of[g] = nloc++;
     blk_nbd[b] = nloc;
     nbd_max = std::max(nbd_max, nloc);
