@@ -469,7 +469,8 @@ def run_c4(args):
 
 
 def run_c5(args, include_bf16=True):
-    """Time to a true relative residual of 1e-10: FP32-inner iterative refinement vs FP64 PCG."""
+    """Time to a true relative residual of 1e-10: FP64 PCG against the mixed-precision solves (FP32 or
+    BF16-operand inner PCG; iterative refinement and reliable updates)."""
     import torch
 
     import paper_2509_10226_amd as tm
@@ -479,36 +480,40 @@ def run_c5(args, include_bf16=True):
     qp, qw = synth.tet_rule(6)
     mesh = tm.Mesh(xyz, tets)
     op64 = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet")
-    res = {}
-    for inner in ("f32", "bf16in", None) if include_bf16 else ("f32", None):
-        opi = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet", precision=inner) if inner else None
-        b = op64.load_vector()
-        op64.solve(b, inner=opi, rtol=1e-10, max_inner=20000)  # warm-up (allocates solver scratch)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        x, st, ok = op64.solve(b, inner=opi, rtol=1e-10, max_inner=20000)
-        torch.cuda.synchronize()
-        res[inner or "f64"] = {"wall_s": round(time.perf_counter() - t0, 4), "converged": bool(ok),
-                               "outer_its": st["outer_its"], "inner_its": st["inner_its"],
-                               "final_relres": st["final_relres"]}
-        del opi
-    # sensitivity of the FP32-inner refinement to the inner tolerance
-    sweep = {}
-    opi = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet", precision="f32")
     b = op64.load_vector()
-    for irt in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+
+    def timed(opi, method="refinement", inner_rtol=1e-4, warm=True):
+        if warm:  # allocates the solver scratch
+            op64.solve(b, inner=opi, rtol=1e-10, inner_rtol=inner_rtol, max_inner=20000, method=method)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, st, ok = op64.solve(b, inner=opi, rtol=1e-10, inner_rtol=irt, max_inner=20000)
+        x, st, ok = op64.solve(b, inner=opi, rtol=1e-10, inner_rtol=inner_rtol, max_inner=20000, method=method)
         torch.cuda.synchronize()
-        sweep[f"{irt:g}"] = {"wall_s": round(time.perf_counter() - t0, 4), "converged": bool(ok),
-                             "outer_its": st["outer_its"], "inner_its": st["inner_its"]}
-    del opi
-    return {"value_s": res["f32"]["wall_s"], "unit": "s", "higher_is_better": False,
-            "fp32_inner_ir_by_inner_rtol": sweep,
-            "fp32_inner_ir": res["f32"], "fp64_pcg": res["f64"],
-            **({"bf16_inner_ir": res["bf16in"]} if include_bf16 else {}),
-            "speedup_fp32_ir_vs_fp64": round(res["f64"]["wall_s"] / res["f32"]["wall_s"], 3),
+        return {"wall_s": round(time.perf_counter() - t0, 4), "converged": bool(ok), "outer_its": st["outer_its"],
+                "inner_its": st["inner_its"], "final_relres": st["final_relres"]}
+
+    res = {"fp64_pcg": timed(None)}
+    ops = {"fp32": tm.Operator(mesh, 3, (qp, qw), bc="dirichlet", precision="f32")}
+    if include_bf16:
+        ops["bf16"] = tm.Operator(mesh, 3, (qp, qw), bc="dirichlet", precision="bf16in")
+    for name, opi in ops.items():
+        res[f"{name}_inner_ir"] = timed(opi, "refinement", 1e-4)
+        res[f"{name}_inner_reliable"] = timed(opi, "reliable", 1e-2)
+    # sensitivity of the FP32-inner solves to the inner tolerance
+    sweep_ir, sweep_ru = {}, {}
+    for irt in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        sweep_ir[f"{irt:g}"] = timed(ops["fp32"], "refinement", irt, warm=False)
+    for irt in (1e-1, 1e-2, 1e-3, 1e-4):
+        sweep_ru[f"{irt:g}"] = timed(ops["fp32"], "reliable", irt, warm=False)
+    del ops
+    t64 = res["fp64_pcg"]["wall_s"]
+    return {"value_s": res["fp32_inner_reliable"]["wall_s"], "unit": "s", "higher_is_better": False, **res,
+            "fp32_inner_ir_by_inner_rtol": sweep_ir, "fp32_inner_reliable_by_inner_rtol": sweep_ru,
+            "speedup_fp32_reliable_vs_fp64": round(t64 / res["fp32_inner_reliable"]["wall_s"], 3),
+            "speedup_fp32_ir_vs_fp64": round(t64 / res["fp32_inner_ir"]["wall_s"], 3),
+            "methods": "ir = iterative refinement (inner PCG restarted per FP64 residual, inner_rtol 1e-4); "
+                       "reliable = one inner PCG with FP64 residual replacement every 1e-2 reduction, "
+                       "search direction kept (FP32)",
             "workload": f"CG P3 Dirichlet Poisson f=1, kappa=1, {n}^3x6 Kuhn tets ({op64.n_free} free DoFs), "
                         "24-point rule, Jacobi-PCG; stop at true FP64 residual 1e-10"}, (mesh, op64, qp, qw)
 

@@ -247,6 +247,7 @@ typedef struct {
   int32_t max_outer;
   int32_t max_inner;   /* also the iteration cap of the plain FP64 PCG */
   int32_t precond;     /* 0 = none, 1 = Jacobi (point diagonal of the operator) */
+  int32_t method;      /* with op_inner: 0 = iterative refinement, 1 = reliable updates (below) */
 } tetmf_solve_opts;
 
 typedef struct {
@@ -257,10 +258,21 @@ typedef struct {
 
 /* Solve A64 x = b (CG, SPD operator) on the GPU.
  *  op_inner == NULL: Jacobi-preconditioned conjugate gradients in FP64.
- *  op_inner (F32 or BF16IN op on the same mesh): iterative refinement with
- *  the FP64 residual r = b - A64 x, an inner Jacobi-PCG on A_inner d = r in
- *  the inner precision (dot products accumulated in FP64), and x += d in
- *  FP64 (mixed precision as in Sec. 4.1).
+ *  op_inner (F32 or BF16IN op on the same mesh), mixed precision as in Sec.
+ *  4.1 (the bulk of the work in the inner precision, every residual that
+ *  decides convergence in FP64; dot products accumulated in FP64):
+ *   method 0, iterative refinement: the FP64 residual r = b - A64 x, an
+ *    inner Jacobi-PCG on A_inner d = r down to inner_rtol ||r||, x += d in
+ *    FP64, repeated (max_outer steps);
+ *   method 1, reliable updates: one inner-precision Jacobi-PCG whose iterate
+ *    is added to x in FP64 and whose residual is replaced by the FP64 true
+ *    residual b - A64 x whenever its recursively updated residual has fallen
+ *    by inner_rtol since the previous replacement (or below rtol ||b|| / 2);
+ *    with an F32 inner op the search direction is kept across a replacement
+ *    while the true and the recursive residual agree (squared norms within a
+ *    factor 4), so no Krylov information is discarded; it is restarted
+ *    otherwise and always with a BF16IN inner op (max_outer caps the
+ *    replacements, max_inner the inner iterations).
  *  b, x: device FP64 [n_components * n_dofs]; x holds x0 on entry (warm start) and the
  *  solution on exit.  kappa: device [n_q][n_cell] for each op's precision or
  *  NULL.  Synchronises the stream.  Returns NOT_CONVERGED when the caps are

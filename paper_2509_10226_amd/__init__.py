@@ -58,7 +58,7 @@ class Info(ctypes.Structure):
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("max_inner", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("max_inner", ctypes.c_int32), ("precond", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -349,11 +349,15 @@ class Operator:
         return b
 
     def solve(self, b, x0=None, kappa=None, inner=None, kappa_inner=None, rtol=1e-10, inner_rtol=1e-4,
-              max_outer=50, max_inner=5000, precond="jacobi"):
-        """Solve A x = b (see tetmf_solve).  Returns (x, stats dict, converged)."""
+              max_outer=50, max_inner=5000, precond="jacobi", method="refinement"):
+        """Solve A x = b (see tetmf_solve; method "refinement" or "reliable"
+        with an inner operator).  Returns (x, stats dict, converged)."""
         torch = _torch()
         x = torch.zeros(self.n_vec, dtype=torch.float64, device=self._device()) if x0 is None else x0.clone()
-        o = SolveOpts(rtol, inner_rtol, max_outer, max_inner, 1 if precond == "jacobi" else 0)
+        if method not in ("refinement", "reliable"):
+            raise ValueError(f"unknown solve method {method!r}")
+        o = SolveOpts(rtol, inner_rtol, max_outer, max_inner, 1 if precond == "jacobi" else 0,
+                      1 if method == "reliable" else 0)
         st = SolveStats()
         status = _check(lib().tetmf_solve(
             self._h, self._p(kappa, torch.float64, self.n_q * self.n_cell, "kappa"),

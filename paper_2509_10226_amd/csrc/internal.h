@@ -99,9 +99,10 @@ hipError_t vec_cast(int prec_src, const void* src, int prec_dst, void* dst, int6
 hipError_t vec_sub(const double* b, const double* a, double* r, int64_t n, hipStream_t s);
 // Fused Jacobi-PCG steps with device-resident FP64 scalars (kernels.hip).
 // part: at least 3 * 512 doubles of partial sums.
-// pcg_init: x = 0, r = rhs, z = dinv r, p = z, *rz = r.z, *rr = r.r.
+// pcg_init: x = 0, r = rhs, z = dinv r, p = z (kept as it is when keep_p),
+// *rz = r.z, *rr = r.r.
 hipError_t pcg_init(int prec, const void* rhs, const void* dinv, void* x, void* r, void* z, void* p, double* part,
-                    double* rz, double* rr, int64_t n, hipStream_t s);
+                    double* rz, double* rr, int64_t n, hipStream_t s, int keep_p = 0);
 // One iteration after q = A p: alpha = rz_old / p.q, x += alpha p,
 // r -= alpha q, z = dinv r, *rz_new = r.z, beta = rz_new / rz_old,
 // p = z + beta p, *rr = r.r, and *pq_out = p.q when pq_out is not NULL.

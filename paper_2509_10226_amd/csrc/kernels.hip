@@ -1547,12 +1547,12 @@ __device__ inline double sum_partials(const double* __restrict__ part, double* s
   return block_sum256(v, sh);
 }
 
-// x = 0, r = rhs, z = dinv r, p = z; partials of r.z and r.r.
+// x = 0, r = rhs, z = dinv r, p = z (unless keep_p); partials of r.z and r.r.
 template <typename T>
 __global__ void __launch_bounds__(256) pcg_init_kernel(const T* __restrict__ rhs, const T* __restrict__ dinv,
                                                        T* __restrict__ x, T* __restrict__ r, T* __restrict__ z,
                                                        T* __restrict__ p, double* __restrict__ part_rz,
-                                                       double* __restrict__ part_rr, long n) {
+                                                       double* __restrict__ part_rr, long n, int keep_p) {
   __shared__ double sh[256];
   double srz = 0, srr = 0;
   for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)kVecBlocks * 256) {
@@ -1560,7 +1560,7 @@ __global__ void __launch_bounds__(256) pcg_init_kernel(const T* __restrict__ rhs
     x[i] = T(0);
     r[i] = ri;
     z[i] = zi;
-    p[i] = zi;
+    if (!keep_p) p[i] = zi;
     srz += (double)ri * (double)zi;
     srr += (double)ri * (double)ri;
   }
@@ -1778,15 +1778,15 @@ hipError_t vec_sub(const double* b, const double* a, double* r, int64_t n, hipSt
 }
 
 hipError_t pcg_init(int prec, const void* rhs, const void* dinv, void* x, void* r, void* z, void* p, double* part,
-                    double* rz, double* rr, int64_t n, hipStream_t s) {
+                    double* rz, double* rr, int64_t n, hipStream_t s, int keep_p) {
   if (prec == PREC_F64)
     hipLaunchKernelGGL(pcg_init_kernel<double>, dim3(kVecBlocks), dim3(256), 0, s, (const double*)rhs,
                        (const double*)dinv, (double*)x, (double*)r, (double*)z, (double*)p, part + kVecBlocks,
-                       part + 2 * kVecBlocks, (long)n);
+                       part + 2 * kVecBlocks, (long)n, keep_p);
   else
     hipLaunchKernelGGL(pcg_init_kernel<float>, dim3(kVecBlocks), dim3(256), 0, s, (const float*)rhs,
                        (const float*)dinv, (float*)x, (float*)r, (float*)z, (float*)p, part + kVecBlocks,
-                       part + 2 * kVecBlocks, (long)n);
+                       part + 2 * kVecBlocks, (long)n, keep_p);
   hipLaunchKernelGGL(pcg_scalars_kernel, dim3(1), dim3(256), 0, s, part + kVecBlocks, part + 2 * kVecBlocks, rz, rr);
   return hipGetLastError();
 }

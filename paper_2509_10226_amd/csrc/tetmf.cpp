@@ -1570,21 +1570,83 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
     check_hip(vec_dot(PREC_F64, b, b, n, part, scal + 10, s), "dot");
     const double bnorm2 = read_scalar(scal + 10, s);
     const double tol2 = opts->rtol * opts->rtol * bnorm2;
-    // Outer loop: FP64 true residual r = b - A64 x, then a Jacobi-PCG solve of
-    // A_inner d = r and x += d.  With an inner operator the inner solve stops
-    // at inner_rtol ||r|| (iterative refinement); without one it runs in FP64
-    // down to rtol ||b|| / 2, so that its recursion-vs-true residual gap
-    // stays below the target, and the outer loop only confirms (or repeats).
+    // Method 0 and the plain FP64 PCG: the FP64 true residual r = b - A64 x,
+    // then a Jacobi-PCG solve of A_inner d = r and x += d.  With an inner
+    // operator the inner solve stops at inner_rtol ||r|| (iterative
+    // refinement); without one it runs in FP64 down to rtol ||b|| / 2, so that
+    // its recursion-vs-true residual gap stays below the target, and the outer
+    // loop only confirms (or repeats).  Method 1: below.
     int outer = 0, inner_total = 0, status = TETMF_NOT_CONVERGED;
     double relres = 1.0;
     const int max_outer = std::max(1, opts->max_outer);
-    for (;; ++outer) {
+    if (opts->method != 0 && opts->method != 1)
+      return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_solve: method must be 0 or 1");
+    // FP64 true residual r64 = b - A64 x, its squared norm, relres
+    auto true_residual = [&]() -> double {
       int st = run_cg(op64, MODE_APPLY, x, nullptr, kappa64, tmp64, nullptr, s);
-      if (st) return st;
+      if (st) throw Error(st, g_last_error);
       check_hip(vec_sub(b, tmp64, r64, n, s), "sub");
       check_hip(vec_dot(PREC_F64, r64, r64, n, part, scal + 11, s), "dot");
       const double rn2 = read_scalar(scal + 11, s);
       relres = bnorm2 > 0 ? std::sqrt(rn2 / bnorm2) : std::sqrt(rn2);
+      return rn2;
+    };
+    if (opi && opts->method == 1) {
+      // Reliable updates: one inner-precision PCG on A_inner d = r (d in id,
+      // added to x in FP64 at every replacement).  Its residual is replaced by
+      // the cast FP64 true residual when the recursive one has fallen by
+      // inner_rtol since the last replacement, or below rtol ||b|| / 2; the
+      // search direction p is kept, and the new r.z enters the next step's
+      // alpha and beta.  The direction is kept only for an FP32 inner
+      // operator and while the true residual agrees with the recursive one
+      // (squared norms within a factor 4); BF16 operands (products symmetric
+      // only to their rounding, about 3e-3) restart it at every replacement,
+      // which makes each step an iterative-refinement step (a kept direction
+      // stalled their recursion).  A non-finite recursive residual discards
+      // the inner iterate and restarts from x.
+      double rn2 = true_residual();
+      const double red2 = opts->inner_rtol * opts->inner_rtol;
+      const int max_inner = std::max(1, opts->max_inner);
+      double* rz = scal + 0;  // double-buffered r.z (iteration it reads rz[it & 1])
+      double* rr = scal + 2;
+      int it = 0;
+      if (rn2 <= tol2) {
+        status = TETMF_OK;
+      } else {
+        check_hip(vec_cast(PREC_F64, r64, kpi, iq, n, s), "cast");
+        check_hip(pcg_init(kpi, iq, idinv, id, ir, iz, ip, part, rz, rr, n, s), "pcg init");
+        double ref2 = read_scalar(rr, s);
+        while (it < max_inner) {
+          int st = run_cg(ow, MODE_APPLY, ip, nullptr, kappai, iq, nullptr, s);
+          if (st) return st;
+          check_hip(pcg_iteration(kpi, id, ir, iz, ip, iq, idinv, part, rz + (it & 1), rz + ((it + 1) & 1), rr,
+                                  nullptr, n, s),
+                    "pcg iteration");
+          ++it;
+          if (it % kCheckEvery != 0 && it != max_inner) continue;
+          const double rr_now = read_scalar(rr, s);
+          const bool finite = std::isfinite(rr_now);
+          if (finite && rr_now > red2 * ref2 && rr_now > 0.25 * tol2 && it != max_inner) continue;
+          // replacement: x += d (FP64), r = b - A64 x
+          if (finite) check_hip(vec_axpy_f64(x, id, kpi, n, s), "axpy");
+          rn2 = true_residual();
+          ++outer;
+          if (rn2 <= tol2) {
+            status = TETMF_OK;
+            break;
+          }
+          if (outer >= max_outer || it >= max_inner) break;
+          const int keep = opi->prec == TETMF_F32 && finite && rn2 <= 4.0 * rr_now ? 1 : 0;
+          check_hip(vec_cast(PREC_F64, r64, kpi, iq, n, s), "cast");
+          check_hip(pcg_init(kpi, iq, idinv, id, ir, iz, ip, part, rz + (it & 1), rr, n, s, keep), "pcg restart");
+          ref2 = read_scalar(rr, s);
+        }
+      }
+      inner_total = it;
+    }
+    // iterative refinement (and the plain FP64 PCG: one outer step)
+    for (; !(opi && opts->method == 1); ++outer) {
+      const double rn2 = true_residual();
       if (rn2 <= tol2) {
         status = TETMF_OK;
         break;

@@ -87,6 +87,16 @@ def test_solve_errors_and_not_converged(ops):
     assert torch.isfinite(x).all()
     x2, st2, ok2 = cg.solve(b, x0=x, rtol=1e-10)  # warm start from the stopped iterate
     assert ok2 and st2["final_relres"] <= 1e-10
+    # reliable updates stopped by their caps, then an unknown method through the C ABI
+    x3, st3, ok3 = cg.solve(b, inner=f32, rtol=1e-14, max_outer=2, max_inner=8, method="reliable")
+    assert not ok3 and st3["inner_its"] <= 8 and st3["outer_its"] <= 2
+    assert torch.isfinite(x3).all()
+    L = tm.lib()
+    xz = torch.zeros_like(b)
+    o = tm.SolveOpts(1e-10, 1e-4, 5, 100, 1, 7)
+    st = tm.SolveStats()
+    assert L.tetmf_solve(cg._h, None, f32._h, None, _p(b), _p(xz), ctypes.byref(o), ctypes.byref(st),
+                         tm._stream()) == INVALID
 
 
 def test_smoother_errors(ops):

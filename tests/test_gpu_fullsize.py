@@ -258,12 +258,14 @@ def test_c5_mixed_precision_solve():
     op32 = tm.Operator(mesh, p, (qp, qw), bc="dirichlet", precision="f32")
     b = op64.load_vector()
     x_ir, st_ir, ok_ir = op64.solve(b, inner=op32, rtol=1e-10, inner_rtol=1e-4)
+    x_ru, st_ru, ok_ru = op64.solve(b, inner=op32, rtol=1e-10, inner_rtol=1e-2, method="reliable")
     x_cg, st_cg, ok_cg = op64.solve(b, rtol=1e-10, max_inner=20000)
-    print(f"C5: FP32-inner IR {st_ir}; FP64 PCG {st_cg}")
-    assert ok_ir and ok_cg
-    assert st_ir["final_relres"] <= 1e-10 and st_cg["final_relres"] <= 1e-10
+    print(f"C5: FP32-inner IR {st_ir}; FP32 reliable updates {st_ru}; FP64 PCG {st_cg}")
+    assert ok_ir and ok_ru and ok_cg
+    assert max(st_ir["final_relres"], st_ru["final_relres"], st_cg["final_relres"]) <= 1e-10
     xi, xc = x_ir.cpu().numpy(), x_cg.cpu().numpy()
     assert np.linalg.norm(xi - xc) <= 1e-8 * np.linalg.norm(xc)
+    assert np.linalg.norm(x_ru.cpu().numpy() - xc) <= 1e-8 * np.linalg.norm(xc)
     # residual of sampled free rows with the oracle: r_i = b_i - sum_j A_ij x_j
     _, dof_xyz, dof_cell = op64.numbering()
     tree = cKDTree(dof_xyz)

@@ -13,8 +13,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("inner", [None, "f32"])
-def test_solve_poisson_dirichlet(inner):
+@pytest.mark.parametrize("inner,method", [(None, "refinement"), ("f32", "refinement"), ("f32", "reliable"),
+                                          ("bf16in", "reliable")])
+def test_solve_poisson_dirichlet(inner, method):
     import paper_2509_10226_amd as tm
     n, p = 6, 3
     xyz, tets = synth.kuhn_cube_mesh(n, 0.15, 0)
@@ -29,7 +30,7 @@ def test_solve_poisson_dirichlet(inner):
     bt = op.load_vector()
     assert rel_err(bt.cpu().numpy(), b[idx]) <= 1e-12
     opi = tm.Operator(mesh, p, (qp, qw), bc="dirichlet", precision=inner) if inner else None
-    x, st, ok = op.solve(bt, inner=opi, rtol=1e-10)
+    x, st, ok = op.solve(bt, inner=opi, rtol=1e-10, method=method)
     assert ok, st
     xs = x.cpu().numpy()
     # true residual with the oracle matrix in oracle order
