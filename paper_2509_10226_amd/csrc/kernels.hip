@@ -1108,13 +1108,35 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
       }
       __builtin_amdgcn_s_setprio(0);
     }
-    // ---- face terms
+    // ---- face terms.  Poisson form: each face's neighbour, relabelling code
+    // and face id are requested one face ahead (115.1 -> 113.7 us at 32^3 x 6,
+    // and no scratch); the mass-term form keeps those registers (it would
+    // spill).
+    constexpr bool kAhead = C == 3;
+    int nbn = 0, coden = 0, fidn = 0;
+    if constexpr (kAhead) {
+      nbn = valid ? d.nb[cell] : -1;
+      coden = valid ? d.code[cell] : 0;
+      fidn = valid ? d.fid[cell] : 0;
+    }
 #pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       const long fi = (long)f * ncp + cell;
-      const int nbc = valid ? d.nb[fi] : -1;
-      const int code = valid ? d.code[fi] : 0;
-      const int fidv = valid ? d.fid[fi] : 0;
+      int nbc, code, fidv;
+      if constexpr (kAhead) {
+        nbc = nbn;
+        code = coden;
+        fidv = fidn;
+        if (f < 3) {
+          nbn = valid ? d.nb[fi + ncp] : -1;
+          coden = valid ? d.code[fi + ncp] : 0;
+          fidn = valid ? d.fid[fi + ncp] : 0;
+        }
+      } else {
+        nbc = valid ? d.nb[fi] : -1;
+        code = valid ? d.code[fi] : 0;
+        fidv = valid ? d.fid[fi] : 0;
+      }
       const int ro = code & 255, rn = (code >> 8) & 255;
       const bool boundary = nbc < 0;
       const bool active = valid && (!boundary || d.dirichlet);
