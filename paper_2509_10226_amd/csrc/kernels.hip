@@ -487,15 +487,28 @@ __device__ inline void point_geo(const T* __restrict__ geo, int ncp, const T* __
 // limit of the forward kernels).  The FP64 backward at P3 stages u and g
 // (about 90 KB of LDS per workgroup at the 64^3 x 6 mesh), so one workgroup
 // fits per CU and two waves per SIMD lose nothing; the budget then allows 256
-// registers instead of spilling at 128.
-template <typename T, int NDOF, int MODE>
+// registers instead of spilling at 128.  Curved FP64 cells take two waves
+// too: they request every point's geometry of a tile at once (see
+// CurvAhead), and the bytes in flight per SIMD outweigh the halved occupancy.
+template <typename T, int NDOF, int MODE, bool CURV>
 struct MinWaves {
-  static constexpr int value = (sizeof(T) == 8 && NDOF == 20 && MODE == MODE_BACKWARD) ? 2 : 4;
+  static constexpr int value =
+      ((sizeof(T) == 8 && NDOF == 20 && MODE == MODE_BACKWARD) || (CURV && sizeof(T) == 8)) ? 2 : 4;
+};
+
+// Curved cells read a geometry and a coefficient per point.  FP64: all of a
+// tile's points are requested before its interpolation (588 -> 582 us at
+// 64^3 x 6, no scratch in any curved FP64 kernel).  FP32: one point at a
+// time, each request tied to the previous point's result (all at once:
+// 330 -> 363 us).
+template <typename T, bool CURV>
+struct CurvAhead {
+  static constexpr bool value = CURV && sizeof(T) == 8;
 };
 
 template <typename T, int NDOF, int NQ, int C, int MODE, bool BF, bool CURV, int NCOMP>
 __global__ void __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE>::value, 8))) cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* __restrict__ kappa,
+__attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE, CURV>::value, 8))) cg_kernel(CGDev d, const T* __restrict__ u, const T* __restrict__ gin, const T* __restrict__ kappa,
           T* __restrict__ out, T* __restrict__ dk) {
   using TL = typename EngineSel<T, NDOF, NQ, C, BF>::type;
   using M = Mfma<T>;
@@ -662,6 +675,13 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE>::value, 8))) cg_kerne
             gb[BWD ? ks : 0] = j < NDOF ? y : T(0);
           }
         }
+        constexpr bool kAhead = CurvAhead<T, CURV>::value;
+        T Gpre[kAhead ? KP : 1][8];
+        if constexpr (kAhead) {
+          const int cc = valid ? cell : nc - 1;
+#pragma unroll
+          for (int k = 0; k < KP; ++k) point_geo<T, NQ, C>(geo, ncp, kappa, nc, k, g, cell, cc, T(0), Gpre[k]);
+        }
         acc_t acc[MT];
         // matrix-core section of the tile at raised wave priority: the
         // arbiter then prefers the waves issuing products over those in
@@ -679,8 +699,8 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE>::value, 8))) cg_kerne
           for (int t = 0; t < MT; ++t) accg[BWD ? t : 0] = tmp[t];
         }
         // point operator D in registers: item s = C k + c at acc[s / 4][s % 4].
-        // Curved cells: the geometry of point k + 1 is requested once point
-        // k - 1 is done (two points' geometry live at a time).
+        // Curved FP32 cells: the geometry of point k is requested once point
+        // k - 1 is done (FP64: all points requested above).
         const int ccell = valid ? cell : nc - 1;
         // per-tile copies of the bases, so that the row addresses derived from
         // them are not hoisted out of the block loop (36 of them at P3)
@@ -690,7 +710,10 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE>::value, 8))) cg_kerne
 #pragma unroll
         for (int k = 0; k < KP; ++k) {
           T Gk[8];
-          if constexpr (CURV) {
+          if constexpr (kAhead) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) Gk[c] = Gpre[kAhead ? k : 0][c];
+          } else if constexpr (CURV) {
             const int ip = C * (k > 0 ? k - 1 : 0);
             point_geo<T, NQ, C>(geot, ncp, kapt, nc, k, g, cell, ccell, acc[ip / 4][ip % 4], Gk);
           } else {
