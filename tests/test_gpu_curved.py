@@ -98,16 +98,25 @@ def test_curved_backward():
     assert rel_err(c["op"].cell_data_to_user(dk).cpu().numpy(), dko) <= 1e-12
 
 
-def test_curved_solve():
+@pytest.mark.parametrize("method", [None, "refinement", "reliable"])
+def test_curved_solve(method):
     """Jacobi-PCG on the curved Helmholtz operator reaches the oracle's
-    direct solution."""
+    direct solution: plain FP64, and with an FP32 curved inner operator
+    (same Jacobians and coefficient) by both mixed-precision methods."""
     import scipy.sparse.linalg as spla
+    import paper_2509_10226_amd as tm
     c = setup_curved(4, 2, 4, mass=1.0, bc="dirichlet")
     A = c["A"].tocsc()
     free = ~c["d"]["constrained"]
     b = np.where(free, synth.uniform(3, synth.STREAM_F, A.shape[0]), 0.0)
     x_ref = spla.spsolve(A, b)
     bt = torch.from_numpy(b[c["idx"]]).to(c["dev"])
-    x, stats, ok = c["op"].solve(bt, kappa=c["kl"], rtol=1e-10)
+    kw = {}
+    if method is not None:
+        op32 = tm.Operator(tm.Mesh(c["xyz"], c["tets"]), 2, (c["qp"], c["qw"]), precision="f32", bc="dirichlet",
+                           sigma=1.0, q_jacobians=c["jac"])
+        kw = dict(inner=op32, kappa_inner=c["kl"].float(), method=method, inner_rtol=1e-2)
+    x, stats, ok = c["op"].solve(bt, kappa=c["kl"], rtol=1e-10, **kw)
     assert ok, stats
+    assert stats["final_relres"] <= 1e-10
     assert rel_err(x.cpu().numpy(), x_ref[c["idx"]]) <= 1e-8

@@ -97,18 +97,27 @@ def test_vector_backward_and_diagonal():
     assert rel_err(dg, np.concatenate([c["A"].diagonal()] * 3)[c["idx3"]]) <= 1e-12
 
 
-def test_vector_solve():
+@pytest.mark.parametrize("method", [None, "reliable"])
+def test_vector_solve(method):
     """Jacobi-PCG on the vector Helmholtz operator (the velocity step of
-    Sec. 4.2) reaches the oracle's direct solution."""
+    Sec. 4.2) reaches the oracle's direct solution: plain FP64, and with an
+    FP32 three-component inner operator by reliable updates."""
     import scipy.sparse.linalg as spla
+    import paper_2509_10226_amd as tm
     c = setup_vec(4, 2, 4, mass=1.0, bc="dirichlet")
     Av = c["Av"].tocsc()
     free = np.concatenate([~c["d"]["constrained"]] * 3)
     b = np.where(free, synth.uniform(3, synth.STREAM_F, Av.shape[0]), 0.0)
     x_ref = spla.spsolve(Av, b)
     bt = torch.from_numpy(b[c["idx3"]]).to(c["dev"])
-    x, stats, ok = c["op"].solve(bt, kappa=c["kl"], rtol=1e-10)
+    kw = {}
+    if method is not None:
+        op32 = tm.Operator(tm.Mesh(c["xyz"], c["tets"]), 2, (c["qp"], c["qw"]), precision="f32", bc="dirichlet",
+                           sigma=1.0, n_components=3)
+        kw = dict(inner=op32, kappa_inner=c["kl"].float(), method=method, inner_rtol=1e-2)
+    x, stats, ok = c["op"].solve(bt, kappa=c["kl"], rtol=1e-10, **kw)
     assert ok, stats
+    assert stats["final_relres"] <= 1e-10
     assert rel_err(x.cpu().numpy(), x_ref[c["idx3"]]) <= 1e-8
 
 
