@@ -725,7 +725,11 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE, CURV>::value, 8))) cg
           const int q = g + 4 * k;
           const T w = s_qw[q];
           const bool qok = valid && q < NQ;
-          const T s = qok ? Gk[7] * w : T(0);
+          // straight cells leave the products unmasked (padded points have
+          // zero weight and zero table rows, padded cells' results are never
+          // stored): 70.2 -> 68.8 us for P2 Helmholtz at 48^3 x 6; curved
+          // cells keep the mask (it holds their register budget)
+          const T s = CURV ? (qok ? Gk[7] * w : T(0)) : Gk[7] * w;
           const int i0 = C * k;
           T x, y, z, val = T(0);
           if (BWD) {
@@ -754,7 +758,8 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE, CURV>::value, 8))) cg
           acc[(i0) / 4][(i0) % 4] = s * (G0 * x + G1 * y + G2 * z);
           acc[(i0 + 1) / 4][(i0 + 1) % 4] = s * (G1 * x + G3 * y + G4 * z);
           acc[(i0 + 2) / 4][(i0 + 2) % 4] = s * (G2 * x + G4 * y + G5 * z);
-          if constexpr (C == 4) acc[(i0 + 3) / 4][(i0 + 3) % 4] = qok ? sigma * w * adet * val : T(0);
+          if constexpr (C == 4)
+            acc[(i0 + 3) / 4][(i0 + 3) % 4] = CURV ? (qok ? sigma * w * adet * val : T(0)) : sigma * w * adet * val;
         }
         if (write_out) {
           if (kLateSlots) load_slots();
