@@ -118,7 +118,13 @@ struct Tile {
   static constexpr int NS = C * KP;
   static constexpr int MT = (NS + 3) / 4;
   static constexpr int KS = (NDOF + 3) / 4;
-  static constexpr int NDP = NDOF + 1;
+  // row length of the basis tables: NDOF + 1 in the global [point][4][row]
+  // layout; in LDS the DoF columns are padded with zeros to 16 (at most 16
+  // DoFs) or to a multiple of 4, plus one (an odd row stride), so that every
+  // K step and every 16-row integration reads its missing columns as zeros
+  // instead of under a per-lane predicate
+  static constexpr int NDPG = NDOF + 1;
+  static constexpr int NDP = (NDOF < 16 ? 16 : 4 * ((NDOF + 3) / 4)) + 1;
   static constexpr int NPT = 4 * KP;
   static constexpr int NMF = NDOF < 16 ? NDOF : 16;
   static constexpr int NVA = NDOF - NMF;
@@ -139,7 +145,7 @@ struct Tile {
     T* s_tab = reinterpret_cast<T*>(lds);
     for (int i = tid; i < TAB; i += nt) {
       const int col = i % NDP, c = (i / NDP) % C, p = i / (NDP * C);
-      s_tab[i] = p < NPT ? gtab[(p * 4 + c) * NDP + col] : T(0);
+      s_tab[i] = (p < NPT && col < NDOF) ? gtab[(p * 4 + c) * NDPG + col] : T(0);
     }
   }
 
@@ -171,8 +177,7 @@ struct Tile {
       acc[t] = acc_t{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const int col = 4 * ks + g;
-        const T a = (NDOF % 4 == 0 || col < NDOF) ? s_tab[base + col] : T(0);
+        const T a = s_tab[base + 4 * ks + g];  // zero columns beyond NDOF
         acc[t] = M::mma(a, ub[ks], acc[t]);
       }
     }
@@ -186,8 +191,7 @@ struct Tile {
         T d = T(0);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-          const int col = 4 * ks + g;
-          const T a = (NDOF % 4 == 0 || col < NDOF) ? s_tab[base + col] : T(0);
+          const T a = s_tab[base + 4 * ks + g];
           d = __builtin_amdgcn_mfma_f64_4x4x4f64(a, ub[ks], d, 0, 0, 0);
         }
         acc[MT - 1][r] = d;
@@ -214,7 +218,7 @@ struct Tile {
         T t = T(0);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          const T a = (NDOF % 4 == 0 || col < NDOF) ? s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + col] : T(0);
+          const T a = s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + col];
           t = __builtin_amdgcn_mfma_f64_4x4x4f64(a, acc[s / 4][s % 4], t, 0, 0, 0);
         }
         v[r] = t;
@@ -222,7 +226,7 @@ struct Tile {
     } else {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const T a = (NMF == 16 || c16 < NMF) ? s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + c16] : T(0);
+        const T a = s_tab[((g + 4 * (s / C)) * C + s % C) * NDP + c16];
         v = M::mma(a, acc[s / 4][s % 4], v);
       }
     }
@@ -278,7 +282,7 @@ struct TileBF {
   using F = Tile<float, NDOF, NQ, C>;
   using M = Mfma<float>;
   typedef typename M::acc_t acc_t;
-  static constexpr int KP = F::KP, NS = F::NS, MT = F::MT, NDP = F::NDP, NPT = F::NPT;
+  static constexpr int KP = F::KP, NS = F::NS, MT = F::MT, NDP = F::NDPG, NPT = F::NPT;
   static constexpr int NMF = F::NMF, NVA = F::NVA;
   static constexpr int KSI = (NS + 7) / 8;
   static constexpr int NB = 8;
@@ -1047,10 +1051,13 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
     const T* tab = static_cast<const T*>(d.tab);
     for (int i = threadIdx.x; i < TC::TAB; i += kThreads) {
       const int col = i % TC::NDP, c = (i / TC::NDP) % C, p = i / (TC::NDP * C);
-      s_tab[i] = p < TC::NPT ? tab[(p * 4 + c) * TC::NDP + col] : T(0);
+      s_tab[i] = (p < TC::NPT && col < NDOF) ? tab[(p * 4 + c) * TC::NDPG + col] : T(0);
     }
     const T* ftab = static_cast<const T*>(d.ftab);
-    for (int i = threadIdx.x; i < TF::TAB; i += kThreads) s_ftab[i] = i < TF::NPT * 4 * TF::NDP ? ftab[i] : T(0);
+    for (int i = threadIdx.x; i < TF::TAB; i += kThreads) {
+      const int col = i % TF::NDP, c = (i / TF::NDP) % 4, p = i / (TF::NDP * 4);
+      s_ftab[i] = (p < TF::NPT && col < NDOF) ? ftab[(p * 4 + c) * TF::NDPG + col] : T(0);
+    }
     for (int i = threadIdx.x; i < TC::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
     for (int i = threadIdx.x; i < TF::NPT; i += kThreads) s_fw[i] = static_cast<const T*>(d.fw)[i];
     for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
@@ -1266,10 +1273,13 @@ dg_grad_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ gv, T* __
     const T* tab = static_cast<const T*>(d.tab);
     for (int i = threadIdx.x; i < TC::TAB; i += kThreads) {
       const int col = i % TC::NDP, c = (i / TC::NDP) % 3, p = i / (TC::NDP * 3);
-      s_tab[i] = p < TC::NPT ? tab[(p * 4 + c) * TC::NDP + col] : T(0);
+      s_tab[i] = (p < TC::NPT && col < NDOF) ? tab[(p * 4 + c) * TC::NDPG + col] : T(0);
     }
     const T* ftab = static_cast<const T*>(d.ftab);
-    for (int i = threadIdx.x; i < TF::TAB; i += kThreads) s_ftab[i] = i < TF::NPT * 4 * TF::NDP ? ftab[i] : T(0);
+    for (int i = threadIdx.x; i < TF::TAB; i += kThreads) {
+      const int col = i % TF::NDP, c = (i / TF::NDP) % 4, p = i / (TF::NDP * 4);
+      s_ftab[i] = (p < TF::NPT && col < NDOF) ? ftab[(p * 4 + c) * TF::NDPG + col] : T(0);
+    }
     for (int i = threadIdx.x; i < TC::NPT; i += kThreads) s_qw[i] = static_cast<const T*>(d.qw)[i];
     for (int i = threadIdx.x; i < TF::NPT; i += kThreads) s_fw[i] = static_cast<const T*>(d.fw)[i];
     for (int i = threadIdx.x; i < 24 * NDOF; i += kThreads) s_perm[i] = d.perm[i];
