@@ -136,8 +136,15 @@ struct Tile {
   // B operand of the interpolation: lane group g supplies DoFs bdof(g, i), i < NB
   static constexpr int NB = KS;
   __device__ static constexpr int bdof(int g, int i) { return 4 * i + g; }
+  // FP32 with four tail DoFs (P3): a second, 16-byte aligned copy of the tail
+  // columns [row][4] after the table, so that each item's four values are one
+  // 16-byte read at an immediate offset (the main table keeps its odd row
+  // stride, which spreads its reads over the banks)
+  static constexpr bool kTailTab = sizeof(T) == 4 && NVA == 4;
+  static constexpr int TABA = (TAB + 3) / 4 * 4;
+  static constexpr int TT = kTailTab ? NPTP * C * 4 : 0;
   // LDS bytes of the engine's tables (a multiple of 16)
-  static constexpr int LDS_BYTES = (TAB * (int)sizeof(T) + 15) / 16 * 16;
+  static constexpr int LDS_BYTES = ((TABA + TT) * (int)sizeof(T) + 15) / 16 * 16;
 
   // Tables from the global [NPT][4][NDOF + 1] layout into LDS (rows of
   // points NPT..NPTP - 1 zero).
@@ -147,6 +154,13 @@ struct Tile {
       const int col = i % NDP, c = (i / NDP) % C, p = i / (NDP * C);
       s_tab[i] = (p < NPT && col < NDOF) ? gtab[(p * 4 + c) * NDPG + col] : T(0);
     }
+    if constexpr (kTailTab) {
+      T* tt = s_tab + TABA;
+      for (int i = tid; i < TT; i += nt) {
+        const int r = i / 4, c = r % C, p = r / C;
+        tt[i] = p < NPT ? gtab[(p * 4 + c) * NDPG + 16 + i % 4] : T(0);
+      }
+    }
   }
 
   __device__ static inline void interpolate(const unsigned char* lds, const T (&ub)[KS], int g, int c16,
@@ -155,7 +169,8 @@ struct Tile {
   }
   __device__ static inline void integrate(const unsigned char* lds, const acc_t (&acc)[MT], int g, int c16, acc_t& v,
                                           T (&vv)[NDOF - (NDOF < 16 ? NDOF : 16) > 0 ? NDOF - (NDOF < 16 ? NDOF : 16) : 1]) {
-    integrate(reinterpret_cast<const T*>(lds), acc, g, c16, v, vv);
+    const T* s_tab = reinterpret_cast<const T*>(lds);
+    integrate<kTailTab>(s_tab, acc, g, c16, v, vv, s_tab + TABA);
   }
 
   // acc[t] = rows (items) of M-tile t for the lane's cell column.
@@ -202,8 +217,10 @@ struct Tile {
   // v: DoFs 0..NMF-1 (element r of lane group g is DoF row(g, r));
   // vv[g] (lane groups g < NVA): DoF 16 + g of the lane's cell; the other
   // entries of vv are not meaningful.
+  // TAILTAB: the FP32 tail reads its four values per item from tt (above)
+  template <bool TAILTAB = false>
   __device__ static inline void integrate(const T* __restrict__ s_tab, const acc_t (&acc)[MT], int g, int c16,
-                                          acc_t& v, T (&vv)[NVA > 0 ? NVA : 1]) {
+                                          acc_t& v, T (&vv)[NVA > 0 ? NVA : 1], const T* __restrict__ tt = nullptr) {
     v = acc_t{0, 0, 0, 0};
     if constexpr (sizeof(T) == 8 && NDOF <= 12) {
       // FP64 with at most 12 DoFs (P1, P2): the 16-row product would be at
@@ -252,9 +269,18 @@ struct Tile {
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
         const T x = acc[s / 4][s % 4];
-        const T* e = s_tab + ((g + 4 * (s / C)) * C + s % C) * NDP + 16;
+        const int row = (g + 4 * (s / C)) * C + s % C;
+        if constexpr (TAILTAB) {
+          const float4 e = *reinterpret_cast<const float4*>(tt + 4 * row);
+          part[0] += e.x * x;
+          part[1 % NVA] += e.y * x;
+          part[2 % NVA] += e.z * x;
+          part[3 % NVA] += e.w * x;
+        } else {
+          const T* e = s_tab + row * NDP + 16;
 #pragma unroll
-        for (int jj = 0; jj < NVA; ++jj) part[jj] += e[jj] * x;
+          for (int jj = 0; jj < NVA; ++jj) part[jj] += e[jj] * x;
+        }
       }
 #pragma unroll
       for (int jj = 0; jj < NVA; ++jj) vv[jj] = sum_rows(part[jj]);
