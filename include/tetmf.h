@@ -127,7 +127,9 @@ typedef struct {
 
 /* Mesh setup (Sec. 2.2 geometry; faces for eq. (7)).
  * xyz: host [n_vert][3]; tets: host [n_cell][4] vertex ids.
- * Errors: INVALID_ARGUMENT (sizes, ids out of range), DEGENERATE_CELL
+ * Errors: INVALID_ARGUMENT (NULL pointers; sizes outside 4 <= n_vert < 2^31
+ * and 1 <= n_cell <= (2^31 - 1) / 4, so an empty mesh is rejected; ids out
+ * of range; non-finite coordinates), DEGENERATE_CELL
  * (|det J| <= 1e-12 (mean edge length)^3), NONCONFORMING_MESH (a triangle in
  * more than two cells).  Inputs are copied; free with tetmf_mesh_destroy. */
 int tetmf_mesh_create(int64_t n_vert, const double* xyz, int64_t n_cell, const int32_t* tets,

@@ -77,6 +77,29 @@ def test_mesh_errors(L):
     assert e.value.status == -3
 
 
+def test_mesh_empty_and_null_inputs(L):
+    """An empty mesh (no cells, or fewer than four vertices) and NULL
+    pointers are argument errors, reported before anything is read."""
+    import ctypes
+    xyz, tets = synth.kuhn_cube_mesh(1)
+    for args in [(xyz, tets[:0]), (xyz[:3], np.zeros((0, 4), np.int32)), (xyz[:0], tets[:0])]:
+        with pytest.raises(L.TetmfError) as e:
+            L.Mesh(*args)
+        assert e.value.status == -1
+    C = L.lib()
+    h = ctypes.c_void_p()
+    x = np.ascontiguousarray(xyz)
+    t = np.ascontiguousarray(tets, dtype=np.int32)
+    assert C.tetmf_mesh_create(x.shape[0], None, t.shape[0], t.ctypes.data, ctypes.byref(h)) == -1
+    assert C.tetmf_mesh_create(x.shape[0], x.ctypes.data, t.shape[0], None, ctypes.byref(h)) == -1
+    assert C.tetmf_mesh_create(x.shape[0], x.ctypes.data, t.shape[0], t.ctypes.data, None) == -1
+    assert C.tetmf_mesh_create(-1, x.ctypes.data, t.shape[0], t.ctypes.data, ctypes.byref(h)) == -1
+    assert h.value is None
+    # the same arrays are accepted once every argument is valid
+    assert C.tetmf_mesh_create(x.shape[0], x.ctypes.data, t.shape[0], t.ctypes.data, ctypes.byref(h)) == 0
+    C.tetmf_mesh_destroy(h)
+
+
 @pytest.mark.parametrize("n,p,qdeg,sigma,bc,ordering", [
     (5, 1, 2, 0.0, "neumann", "locality"),
     (6, 2, 4, 1.0, "dirichlet", "locality"),
