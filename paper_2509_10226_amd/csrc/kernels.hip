@@ -21,8 +21,9 @@
 // the point operator D runs in registers, and the result is directly the B
 // operand of the integration product (its K index is (point 4t+g, component r)).
 //
-// The E table lives in LDS ([point][component][NDOF+1], the odd stride keeps
-// the 16 lanes that read one column on distinct banks).
+// The E table lives in LDS ([point][component][NDP]: the DoF columns padded
+// with zeros to 16, or to a multiple of 4, plus one; the odd stride keeps the
+// 16 lanes that read one column on distinct banks).
 #include "internal.h"
 #include "lane_map.h"
 
@@ -104,11 +105,12 @@ __device__ inline double sum_rows(double x) {
 // integration product.  With C = 3 (no value needed) the 24-point rule fills
 // 5 M-tiles instead of 6.
 //
-// The basis table in LDS is [4 KP points][C][NDOF + 1] (rows beyond the rule
-// are zero).  The integration runs the first 16 DoFs on the matrix cores; the
-// remaining NDOF - 16 DoFs (4 at p = 3), which would fill a second 16-row
-// tile to a quarter, are integrated on the vector ALUs and summed over the
-// four lane groups with cross-lane shuffles (the same fixed order in every
+// The basis table in LDS is [NPTP points][C][NDP] (rows beyond the rule and
+// columns beyond the DoFs are zero).  The integration runs the first 16 DoFs
+// on the 16-row matrix-core product; the remaining NDOF - 16 DoFs (4 at
+// p = 3), which would fill a second 16-row tile to a quarter, run in FP64 on
+// the 4x4x4 four-block product, and in FP32 on the vector ALUs, summed over
+// the four lane groups with cross-lane shuffles (the same fixed order in every
 // lane, so the result is identical in all of them).
 template <typename T, int NDOF, int NQ, int C>
 struct Tile {
@@ -271,11 +273,12 @@ struct Tile {
         const T x = acc[s / 4][s % 4];
         const int row = (g + 4 * (s / C)) * C + s % C;
         if constexpr (TAILTAB) {
+          static_assert(NVA == 4, "the aligned tail copy holds four columns");
           const float4 e = *reinterpret_cast<const float4*>(tt + 4 * row);
           part[0] += e.x * x;
-          part[1 % NVA] += e.y * x;
-          part[2 % NVA] += e.z * x;
-          part[3 % NVA] += e.w * x;
+          part[1] += e.y * x;
+          part[2] += e.z * x;
+          part[3] += e.w * x;
         } else {
           const T* e = s_tab + row * NDP + 16;
 #pragma unroll

@@ -76,8 +76,9 @@ def test_vector_components_are_independent():
     assert torch.count_nonzero(v2[:n]) == 0 and torch.count_nonzero(v2[2 * n:]) == 0
 
 
-def test_vector_backward_and_diagonal():
-    c = setup_vec(4, 2, 4, mass=0.5, bc="dirichlet")
+@pytest.mark.parametrize("p,qdeg", [(2, 4), (3, 6)])
+def test_vector_backward_and_diagonal(p, qdeg):
+    c = setup_vec(4, p, qdeg, mass=0.5, bc="dirichlet")
     n = c["A"].shape[0]
     u = synth.uniform(2, synth.STREAM_U, 3 * n)
     g = synth.uniform(2, synth.STREAM_F, 3 * n)
@@ -90,7 +91,7 @@ def test_vector_backward_and_diagonal():
     free = ~c["d"]["constrained"]
     mask = np.concatenate([free] * 3).astype(np.float64)
     dko = oracle.vector_kappa_grad(
-        lambda a, b: oracle.cg_kappa_grad(c["xyz"], c["tets"], 2, c["qp"], c["qw"], a, b, dofs=c["d"]),
+        lambda a, b: oracle.cg_kappa_grad(c["xyz"], c["tets"], p, c["qp"], c["qw"], a, b, dofs=c["d"]),
         u * mask, g * mask, 3, n)
     assert rel_err(c["op"].cell_data_to_user(dk).cpu().numpy(), dko) <= 1e-12
     dg = c["op"].diagonal(c["kl"]).cpu().numpy()
