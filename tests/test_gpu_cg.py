@@ -37,7 +37,17 @@ def setup_case(n, p, qdeg, kappa_sigma=None, mass=0.0, bc="neumann", precision="
     idx = cg_map(dxyz, d["xyz"], 1.0 / n)
     dev = torch.device("cuda", 0)
     kl = None if kap is None else op.cell_data_to_library(torch.from_numpy(kap).to(dev))
-    return dict(A=A, d=d, op=op, idx=idx, kap=kap, kl=kl, dev=dev, xyz=xyz, tets=tets, qp=qp, qw=qw)
+    return dict(A=A, d=d, op=op, idx=idx, kap=kap, kl=kl, dev=dev, xyz=xyz, tets=tets, qp=qp, qw=qw, p=p, bc=bc)
+
+
+def mass_share(c, u, kappa_sigma):
+    """||A u - K u|| / ||A u||: the part of the result the mass term makes
+    (K: the same operator without it)."""
+    kap = c["kap"]
+    K, _ = oracle.assemble_cg(c["xyz"], c["tets"], c["p"], c["qp"], c["qw"], kappa=kap, sigma=0.0,
+                              dirichlet=c["bc"] == "dirichlet")
+    y = c["A"] @ u
+    return float(np.linalg.norm(y - K @ u) / np.linalg.norm(y))
 
 
 def run_apply(c, u):
@@ -189,16 +199,21 @@ def test_cg_backward_vs_oracle(p, qdeg, n, mass, bc, precision):
     assert rel_err(dku, dko) <= TOL[precision]
 
 
-@pytest.mark.parametrize("p,qdeg,mass", [(3, 6, 0.0), (2, 4, 1.0), (3, 4, 0.0)])
-def test_cg_apply_bf16_operands(p, qdeg, mass):
+@pytest.mark.parametrize("p,qdeg,mass,bc", [(3, 6, 0.0, "neumann"), (2, 4, 1000.0, "neumann"), (3, 4, 0.0, "neumann"),
+                                         (1, 2, 500.0, "neumann"), (3, 6, 3000.0, "dirichlet")])
+def test_cg_apply_bf16_operands(p, qdeg, mass, bc):
     """BF16 operands with FP32 accumulation: the error against the FP64 oracle
     is reported, not gated at FP32 level.  The bound here (3e-2) only guards
     against layout mistakes, which give O(1) errors; the measured value is
-    printed."""
-    c = setup_case(5, p, qdeg, kappa_sigma=1.0, mass=mass, precision="bf16in")
+    printed.  The Helmholtz cases take a mass coefficient large enough for
+    the mass term to be a sizeable part of the result (at sigma = 1 it is
+    below 0.1 % on these meshes, under the bound)."""
+    c = setup_case(5, p, qdeg, kappa_sigma=1.0, mass=mass, bc=bc, precision="bf16in")
     u = synth.uniform(0, synth.STREAM_U, c["A"].shape[0])
     y = c["A"] @ u
+    if mass > 0:
+        assert mass_share(c, u, kappa_sigma=1.0) > 0.2
     v = run_apply(c, u)
     err = rel_err(v, y[c["idx"]])
-    print(f"BF16-operand apply, P{p} degree-{qdeg} rule, sigma={mass}: relative error {err:.3e}")
+    print(f"BF16-operand apply, P{p} degree-{qdeg} rule, sigma={mass}, {bc}: relative error {err:.3e}")
     assert err <= 3e-2

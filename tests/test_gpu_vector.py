@@ -76,26 +76,34 @@ def test_vector_components_are_independent():
     assert torch.count_nonzero(v2[:n]) == 0 and torch.count_nonzero(v2[2 * n:]) == 0
 
 
-@pytest.mark.parametrize("p,qdeg", [(2, 4), (3, 6)])
-def test_vector_backward_and_diagonal(p, qdeg):
-    c = setup_vec(4, p, qdeg, mass=0.5, bc="dirichlet")
+@pytest.mark.parametrize("p,qdeg,precision,curved", [
+    (2, 4, "f64", False), (3, 6, "f64", False), (3, 6, "f32", False), (3, 6, "f64", True), (2, 4, "f32", True),
+])
+def test_vector_backward_and_diagonal(p, qdeg, precision, curved):
+    c = setup_vec(4, p, qdeg, mass=0.5, bc="dirichlet", precision=precision, curved=curved)
+    tol = TOL[precision]
     n = c["A"].shape[0]
     u = synth.uniform(2, synth.STREAM_U, 3 * n)
     g = synth.uniform(2, synth.STREAM_F, 3 * n)
-    ut = torch.from_numpy(u[c["idx3"]]).to(c["dev"])
-    gt = torch.from_numpy(g[c["idx3"]]).to(c["dev"])
+    if precision != "f64":
+        u = u.astype(np.float32).astype(np.float64)
+        g = g.astype(np.float32).astype(np.float64)
+    dt = c["op"].dtype
+    ut = torch.from_numpy(u[c["idx3"]]).to(c["dev"], dt)
+    gt = torch.from_numpy(g[c["idx3"]]).to(c["dev"], dt)
     du, dk = c["op"].backward(ut, gt, c["kl"])
-    assert rel_err(du.cpu().numpy(), (c["Av"].T @ g)[c["idx3"]]) <= 1e-12
+    assert rel_err(du.double().cpu().numpy(), (c["Av"].T @ g)[c["idx3"]]) <= tol
     # constrained DoFs enter neither side's gradient: the oracle's form uses
     # the Dirichlet-masked vectors
     free = ~c["d"]["constrained"]
     mask = np.concatenate([free] * 3).astype(np.float64)
     dko = oracle.vector_kappa_grad(
-        lambda a, b: oracle.cg_kappa_grad(c["xyz"], c["tets"], p, c["qp"], c["qw"], a, b, dofs=c["d"]),
+        lambda a, b: oracle.cg_kappa_grad(c["xyz"], c["tets"], p, c["qp"], c["qw"], a, b, dofs=c["d"],
+                                          jac=c["jac"]),
         u * mask, g * mask, 3, n)
-    assert rel_err(c["op"].cell_data_to_user(dk).cpu().numpy(), dko) <= 1e-12
-    dg = c["op"].diagonal(c["kl"]).cpu().numpy()
-    assert rel_err(dg, np.concatenate([c["A"].diagonal()] * 3)[c["idx3"]]) <= 1e-12
+    assert rel_err(c["op"].cell_data_to_user(dk).double().cpu().numpy(), dko) <= tol
+    dg = c["op"].diagonal(c["kl"]).double().cpu().numpy()
+    assert rel_err(dg, np.concatenate([c["A"].diagonal()] * 3)[c["idx3"]]) <= tol
 
 
 @pytest.mark.parametrize("method", [None, "reliable"])
