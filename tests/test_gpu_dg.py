@@ -33,13 +33,18 @@ def setup_dg(n, p, bc="dirichlet", kappa=True, precision="f64", shuffle=False, s
 
 @pytest.mark.parametrize("p", [1, 2, 3])
 @pytest.mark.parametrize("bc", ["dirichlet", "neumann"])
-def test_dg_apply(p, bc):
-    c = setup_dg(4, p, bc=bc)
+@pytest.mark.parametrize("precision,mass", [("f64", 0.0), ("f64", 0.5), ("f32", 0.0), ("f32", 0.5)])
+def test_dg_apply(p, bc, precision, mass):
+    tol = 1e-12 if precision == "f64" else 1e-5
+    c = setup_dg(4, p, bc=bc, precision=precision, mass=mass)
     u = synth.uniform(0, synth.STREAM_U, c["A"].shape[0])
+    if precision != "f64":
+        u = u.astype(np.float32).astype(np.float64)
     y = c["A"] @ u
-    v = c["op"].apply(torch.from_numpy(u[c["idx"]]).to(c["dev"]), c["klc"], c["klf"]).cpu().numpy()
-    assert rel_err(v, y[c["idx"]]) <= 1e-12
-    assert row_err(v, c["A"], u, c["idx"]) <= 1e-12
+    ut = torch.from_numpy(u[c["idx"]]).to(c["dev"], c["op"].dtype)
+    v = c["op"].apply(ut, c["klc"], c["klf"]).double().cpu().numpy()
+    assert rel_err(v, y[c["idx"]]) <= tol
+    assert row_err(v, c["A"], u, c["idx"]) <= tol
 
 
 def test_dg_apply_f32_shuffled_unit_kappa():
