@@ -1529,6 +1529,8 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
                 opi->ncomp != op64->ncomp))
       return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_solve: inner operator does not match op64");
     if ((const void*)b == (const void*)x) return fail(TETMF_ERR_ALIAS, "tetmf_solve: b and x alias");
+    if (opts->method != 0 && opts->method != 1)
+      return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_solve: method must be 0 or 1");
     DeviceScope dsc(op64->device);
     hipStream_t s = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
@@ -1579,8 +1581,6 @@ extern "C" int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* opi, c
     int outer = 0, inner_total = 0, status = TETMF_NOT_CONVERGED;
     double relres = 1.0;
     const int max_outer = std::max(1, opts->max_outer);
-    if (opts->method != 0 && opts->method != 1)
-      return fail(TETMF_ERR_INVALID_ARGUMENT, "tetmf_solve: method must be 0 or 1");
     // FP64 true residual r64 = b - A64 x, its squared norm, relres
     auto true_residual = [&]() -> double {
       int st = run_cg(op64, MODE_APPLY, x, nullptr, kappa64, tmp64, nullptr, s);
