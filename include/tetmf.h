@@ -32,9 +32,14 @@
  *    cell centroids) and numbers DoFs by first touch in that order.
  *    tetmf_op_numbering() exports the maps back to the user's order.
  *  - Cell quadrature data (coefficients, coefficient gradients, source
- *    samples) use the layout [n_q][n_cell] in library cell order; point q of
- *    a cell is X0 + J x_q with J = [X1-X0 | X2-X0 | X3-X0] built from the
- *    cell's vertices in the user's order (vertices are never reordered).
+ *    samples) use the library layout [ceil(n_cell / 16)][n_q][16]: library
+ *    cells in tiles of 16, and the value at point q of library cell i at
+ *    index ((i / 16) n_q + q) 16 + i % 16, so that one tile's data is one
+ *    contiguous run (tetmf_info.n_cell_data = 16 n_q ceil(n_cell / 16)
+ *    entries; the padding entries of a partly used last tile are ignored on
+ *    input and written as zero by the library).  Point q of a cell is
+ *    X0 + J x_q with J = [X1-X0 | X2-X0 | X3-X0] built from the cell's
+ *    vertices in the user's order (vertices are never reordered).
  *  - Face quadrature data use [n_qf][n_face] with faces in canonical order
  *    (lexicographic order of the sorted global vertex triples) and point q
  *    at a + s_q (b - a) + t_q (c - a) for the sorted vertices a < b < c.
@@ -123,6 +128,7 @@ typedef struct {
   int32_t n_components;    /* 1, or 3 for a vector field (vectors hold n_components * n_dofs values) */
   double flops_per_backward; /* algorithmic work of one tetmf_apply_backward with every output */
   double bytes_per_backward;
+  int64_t n_cell_data;     /* entries of a cell-data array in library layout: 16 n_q ceil(n_cell / 16) */
 } tetmf_info;
 
 /* Mesh setup (Sec. 2.2 geometry; faces for eq. (7)).
@@ -175,16 +181,17 @@ int tetmf_op_check(const tetmf_mesh* mesh, const tetmf_op_desc* desc, int64_t* n
 int tetmf_op_numbering(const tetmf_op* op, int32_t* cell_perm, double* dof_xyz, int32_t* dof_cell);
 
 /* Reorder per-point cell data from user layout [n_cell][n_q] (user cell
- * order, FP64, device) to library layout [n_q][n_cell] in the op precision
- * (FP32 for F32 and BF16IN), or back (to_user != 0; library layout in the op
- * precision to user layout in FP64). */
+ * order, FP64, device) to the library layout (n_cell_data entries, see the
+ * top of this file) in the op precision (FP32 for F32 and BF16IN), or back
+ * (to_user != 0; library layout in the op precision to user layout in
+ * FP64). */
 int tetmf_cell_data_layout(const tetmf_op* op, const void* src, void* dst, int to_user, void* stream);
 
 /* v = A(kappa) u  (eq. (5) CG / eq. (7) DG), deterministic: the result is
  * bitwise reproducible for fixed inputs.
  *  u, v: device [n_components * n_dofs] in the op precision (FP32 for BF16IN); must not
  *        alias (ALIAS).
- *  kappa_cell: device [n_q][n_cell] or NULL (kappa = 1).
+ *  kappa_cell: device, library cell-data layout (n_cell_data entries), or NULL (kappa = 1).
  *  kappa_face: DG only, device [n_qf][n_face] or NULL (kappa = 1).
  *  CG DIRICHLET: constrained entries v_c = u_c; constrained u_c do not enter
  *  the free rows (masked gather, Sec. 2.4). */
@@ -217,13 +224,15 @@ int tetmf_apply_noalloc(tetmf_op* op, const void* u, const void* kappa_cell, con
  * backward; these follow from differentiating the forms):
  *  du = A^T g (= A g, both forms are symmetric) and the derivatives of
  *  g^T A(kappa) u with respect to the coefficients:
- *  dkappa_cell[q][e] = w_q |det J_e| (grad u . grad g)(x_q)            (CG, DG)
+ *  dkappa_cell(q, e) = w_q |det J_e| (grad u . grad g)(x_q)            (CG, DG)
  *  dkappa_face[q][F] (DG only) = omega_q (tau [[u]][[g]] - {{d_n u}}[[g]]
  *        - [[u]]{{d_n g}}) on an interior face, omega_q (2 tau u g - g d_n u
  *        - u d_n g) on a Dirichlet boundary face, 0 on a Neumann one.
  * du, dkappa_cell or dkappa_face may be NULL; kappa_face and dkappa_face must
  * be NULL for CG (INVALID_ARGUMENT).  Outputs must not alias each other or an
- * input (ALIAS).  Layouts as for tetmf_apply.  UNSUPPORTED for BF16IN. */
+ * input (ALIAS).  Layouts as for tetmf_apply (dkappa_cell in the library
+ * cell-data layout, its padding entries set to zero).  UNSUPPORTED for
+ * BF16IN. */
 int tetmf_apply_backward(tetmf_op* op, const void* u, const void* g, const void* kappa_cell,
                          const void* kappa_face, void* du, void* dkappa_cell, void* dkappa_face,
                          void* stream);
@@ -238,8 +247,8 @@ int tetmf_diagonal(tetmf_op* op, const void* kappa_cell, const void* kappa_face,
 /* Load vector: the right-hand side b(phi_i) of eq. (2) for the source f of
  * eq. (1), b_i = (f, phi_i) =
  * sum_e sum_q w_q |det J| f_{e,q} phi_i(x_q) (CG), with the cell rule of the
- * operator; zero on constrained rows.  f: device [n_q][n_cell] in the op
- * precision or NULL (f = 1).  b: device [n_dofs].  UNSUPPORTED for SIPG and
+ * operator; zero on constrained rows.  f: device, library cell-data layout
+ * in the op precision, or NULL (f = 1).  b: device [n_dofs].  UNSUPPORTED for SIPG and
  * for vector fields. */
 int tetmf_load_vector(tetmf_op* op, const void* f, void* b, void* stream);
 
@@ -276,8 +285,8 @@ typedef struct {
  *    otherwise and always with a BF16IN inner op (max_outer caps the
  *    replacements, max_inner the inner iterations).
  *  b, x: device FP64 [n_components * n_dofs]; x holds x0 on entry (warm start) and the
- *  solution on exit.  kappa: device [n_q][n_cell] for each op's precision or
- *  NULL.  Synchronises the stream.  Returns NOT_CONVERGED when the caps are
+ *  solution on exit.  kappa: device, library cell-data layout, for each op's
+ *  precision, or NULL.  Synchronises the stream.  Returns NOT_CONVERGED when the caps are
  *  reached. */
 int tetmf_solve(tetmf_op* op64, const void* kappa64, tetmf_op* op_inner, const void* kappa_inner,
                 const double* b, double* x, const tetmf_solve_opts* opts, tetmf_solve_stats* stats,

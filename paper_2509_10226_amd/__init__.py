@@ -53,6 +53,7 @@ class Info(ctypes.Structure):
         ("flops_per_apply", ctypes.c_double), ("bytes_per_apply", ctypes.c_double),
         ("device_bytes", ctypes.c_int64), ("n_components", ctypes.c_int32),
         ("flops_per_backward", ctypes.c_double), ("bytes_per_backward", ctypes.c_double),
+        ("n_cell_data", ctypes.c_int64),
     ]
 
 
@@ -254,6 +255,8 @@ class Operator:
         self.n_face = self.info["n_face"]
         self.n_q = self.info["n_q"]
         self.n_qf = self.info["n_qf"]
+        # entries of per-point cell data in library layout (16-cell tiles)
+        self.n_cell_data = self.info["n_cell_data"]
 
     def __del__(self):
         if getattr(self, "_h", None) and _LIB is not None:
@@ -281,20 +284,26 @@ class Operator:
         torch = _torch()
         return torch.device("cuda", self.device)
 
+    def cell_data_index(self, q, cell):
+        """Index of point q of library cell ``cell`` in library-layout cell
+        data: tiles of 16 cells, [ceil(n_cell / 16)][n_q][16]."""
+        return ((cell >> 4) * self.n_q + q) * 16 + (cell & 15)
+
     def cell_data_to_library(self, data_user):
-        """[n_cell, n_q] FP64 (user order) -> [n_q, n_cell] op dtype (library order), on the GPU."""
+        """[n_cell, n_q] FP64 (user order) -> library layout (n_cell_data
+        entries, op dtype, library cell order), on the GPU."""
         torch = _torch()
         src = data_user.to(device=self._device(), dtype=torch.float64).contiguous()
         if src.shape != (self.n_cell, self.n_q):
             raise ValueError(f"expected [{self.n_cell}, {self.n_q}]")
-        dst = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=self._device())
+        dst = torch.empty(self.n_cell_data, dtype=self.dtype, device=self._device())
         _check(lib().tetmf_cell_data_layout(self._h, self._p(src), self._p(dst), 0, _stream(self.device)))
         return dst
 
     def cell_data_to_user(self, data_lib):
         torch = _torch()
         dst = torch.empty((self.n_cell, self.n_q), dtype=torch.float64, device=self._device())
-        _check(lib().tetmf_cell_data_layout(self._h, self._p(data_lib, self.dtype, self.n_cell * self.n_q),
+        _check(lib().tetmf_cell_data_layout(self._h, self._p(data_lib, self.dtype, self.n_cell_data),
                                             self._p(dst), 1, _stream(self.device)))
         return dst
 
@@ -303,7 +312,7 @@ class Operator:
         if out is None:
             out = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
         _check(lib().tetmf_apply(self._h, self._p(u, self.dtype, self.n_vec, "u"),
-                                 self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                 self._p(kappa_cell, self.dtype, self.n_cell_data, "kappa_cell"),
                                  self._p(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
                                  self._p(out, self.dtype, self.n_vec, "v"), _stream(self.device)))
         return out
@@ -312,7 +321,7 @@ class Operator:
         """v = A(kappa) u into the caller's ``out`` with the library's fixed
         scratch (tetmf_apply_noalloc): nothing is allocated."""
         _check(lib().tetmf_apply_noalloc(self._h, self._p(u, self.dtype, self.n_vec, "u"),
-                                         self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                         self._p(kappa_cell, self.dtype, self.n_cell_data, "kappa_cell"),
                                          self._p(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
                                          self._p(out, self.dtype, self.n_vec, "v"), _stream(self.device)))
         return out
@@ -325,11 +334,11 @@ class Operator:
         torch = _torch()
         dev = self._device()
         du = torch.empty(self.n_vec, dtype=self.dtype, device=dev) if need_du else None
-        dk = torch.empty((self.n_q, self.n_cell), dtype=self.dtype, device=dev) if need_dkappa else None
+        dk = torch.empty(self.n_cell_data, dtype=self.dtype, device=dev) if need_dkappa else None
         dkf = torch.empty((self.n_qf, self.n_face), dtype=self.dtype, device=dev) if need_dkappa_face else None
         _check(lib().tetmf_apply_backward(self._h, self._p(u, self.dtype, self.n_vec, "u"),
                                           self._p(g, self.dtype, self.n_vec, "g"),
-                                          self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+                                          self._p(kappa_cell, self.dtype, self.n_cell_data, "kappa_cell"),
                                           self._p(kappa_face, self.dtype, self.n_qf * self.n_face, "kappa_face"),
                                           self._p(du), self._p(dk), self._p(dkf), _stream(self.device)))
         return (du, dk, dkf) if need_dkappa_face else (du, dk)
@@ -337,14 +346,14 @@ class Operator:
     def diagonal(self, kappa_cell=None):
         torch = _torch()
         d = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_diagonal(self._h, self._p(kappa_cell, self.dtype, self.n_q * self.n_cell, "kappa_cell"),
+        _check(lib().tetmf_diagonal(self._h, self._p(kappa_cell, self.dtype, self.n_cell_data, "kappa_cell"),
                                     None, self._p(d), _stream(self.device)))
         return d
 
     def load_vector(self, f=None):
         torch = _torch()
         b = torch.empty(self.n_dofs, dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_load_vector(self._h, self._p(f, self.dtype, self.n_q * self.n_cell, "f"), self._p(b),
+        _check(lib().tetmf_load_vector(self._h, self._p(f, self.dtype, self.n_cell_data, "f"), self._p(b),
                                        _stream(self.device)))
         return b
 
@@ -360,7 +369,7 @@ class Operator:
                       1 if method == "reliable" else 0)
         st = SolveStats()
         status = _check(lib().tetmf_solve(
-            self._h, self._p(kappa, torch.float64, self.n_q * self.n_cell, "kappa"),
+            self._h, self._p(kappa, torch.float64, self.n_cell_data, "kappa"),
             inner._h if inner is not None else None,
             self._p(kappa_inner, inner.dtype if inner is not None else None, None, "kappa_inner"),
             self._p(b, torch.float64, self.n_vec, "b"), self._p(x, torch.float64, self.n_vec, "x"),
@@ -376,7 +385,7 @@ class Operator:
         zero = x is None
         if zero:
             x = torch.empty(self.n_vec, dtype=self.dtype, device=self._device())
-        _check(lib().tetmf_chebyshev(self._h, self._p(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
+        _check(lib().tetmf_chebyshev(self._h, self._p(kappa, self.dtype, self.n_cell_data, "kappa"),
                                      self._p(inv_diag, self.dtype, self.n_vec, "inv_diag"),
                                      self._p(b, self.dtype, self.n_vec, "b"), self._p(x, self.dtype, self.n_vec, "x"),
                                      int(degree), float(lambda_min), float(lambda_max), 1 if zero else 0, _stream(self.device)))
@@ -386,7 +395,7 @@ class Operator:
         """Lanczos estimate of the largest eigenvalue of D^-1 A (see
         tetmf_estimate_lambda_max)."""
         lam = ctypes.c_double()
-        _check(lib().tetmf_estimate_lambda_max(self._h, self._p(kappa, self.dtype, self.n_q * self.n_cell, "kappa"),
+        _check(lib().tetmf_estimate_lambda_max(self._h, self._p(kappa, self.dtype, self.n_cell_data, "kappa"),
                                                self._p(inv_diag, self.dtype, self.n_vec, "inv_diag"), int(n_iter),
                                                ctypes.byref(lam), _stream(self.device)))
         return lam.value
@@ -451,7 +460,7 @@ _APPLY_FN = None
 
 
 def apply_autograd(op, u, kappa, kappa_face=None):
-    """Differentiable v = A(kappa) u (kappa in library layout [n_q, n_cell];
+    """Differentiable v = A(kappa) u (kappa in library layout, op.n_cell_data entries;
     kappa_face, DG only, [n_qf, n_face])."""
     global _APPLY_FN
     if _APPLY_FN is None:

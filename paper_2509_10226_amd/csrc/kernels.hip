@@ -504,12 +504,14 @@ __device__ inline void point_geo(const T* __restrict__ geo, int ncp, const T* __
                                  int g, int cell, int cc, T dep, T (&G)[8]) {
   const int q = min(g + 4 * k, NQ - 1);
   uint32_t off = ((uint32_t)(q - 4 * k) * (uint32_t)ncp + (uint32_t)cell) * (uint32_t)sizeof(T);
-  uint32_t kof = ((uint32_t)(q - 4 * k) * (uint32_t)nc + (uint32_t)cc) * (uint32_t)sizeof(T);
+  // coefficient: tile base of the clamped cell and an offset inside its tile
+  uint32_t kof = (uint32_t)lanes::cell_data_index(NQ, q, cc & 15) * (uint32_t)sizeof(T);
   asm volatile("" : "+v"(off), "+v"(kof) : "v"(dep));
 #pragma unroll
   for (int c = 0; c < (C == 4 ? 7 : 6); ++c) G[c] = load_at(geo + ((long)c * NQ + 4 * k) * ncp, off);
   if (C != 4) G[6] = T(0);
-  G[7] = kappa ? load_at(kappa + (long)(4 * k) * nc, kof) : T(1);
+  G[7] = kappa ? load_at(kappa + lanes::cell_data_index(NQ, 0, cc & ~15), kof) : T(1);
+  (void)nc;
 }
 
 // NCOMP > 1: a vector field of NCOMP components without coupling (Sec. 3.2),
@@ -661,14 +663,13 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE, CURV>::value, 8))) cg
           // loaded with the per-point geometry
         } else if (kappa) {
           const int cc = valid ? cell : nc - 1;
-          // row base 4k and a lane row below 4 (the lane's point in a full
-          // group, clamped in a partly used last one): the 32-bit offset
-          // stays below 4 nc sizeof(T)
+          // the tile's contiguous run (base) and the lane's point and cell
+          // inside it (a 32-bit offset below 16 NQ sizeof(T))
+          const T* kt = kappa + lanes::cell_data_index(NQ, 0, cc & ~15);
 #pragma unroll
           for (int k = 0; k < KP; ++k)
-            kq[k] = load_at(kappa + (long)(4 * k) * nc,
-                            ((uint32_t)lanes::kappa_lane_row(NQ, g, k) * (uint32_t)nc + (uint32_t)cc) *
-                                (uint32_t)sizeof(T));
+            kq[k] = load_at(kt, (uint32_t)lanes::cell_data_index(NQ, 4 * k + lanes::kappa_lane_row(NQ, g, k), cc & 15) *
+                                    (uint32_t)sizeof(T));
         } else {
 #pragma unroll
           for (int k = 0; k < KP; ++k) kq[k] = T(1);
@@ -777,10 +778,11 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE, CURV>::value, 8))) cg
                                uz * (G2 * x + G4 * y + G5 * z));
             // vector fields: the sum over the components, in component order
             if (dk && qok) {
+              const long di = lanes::cell_data_index(NQ, q, cell);
               if (comp == 0)
-                dk[(long)q * nc + cell] = dkv;
+                dk[di] = dkv;
               else
-                dk[(long)q * nc + cell] += dkv;
+                dk[di] += dkv;
             }
           } else {
             x = acc[(i0) / 4][(i0) % 4];
@@ -859,7 +861,7 @@ __global__ void __launch_bounds__(kThreads) cg_vec_kernel(CGDev d, const T* __re
         const T G3 = geo[3 * gs + gr], G4 = geo[4 * gs + gr], G5 = geo[5 * gs + gr];
         const T adet = geo[6 * gs + gr];
         const T w = qw[q];
-        const T c = kappa ? kappa[(long)q * nc + cell] : T(1);
+        const T c = kappa ? kappa[lanes::cell_data_index(NQ, q, cell)] : T(1);
         const T x = s_tab[(q * 4 + 0) * NDP + j], y = s_tab[(q * 4 + 1) * NDP + j];
         const T z = s_tab[(q * 4 + 2) * NDP + j], val = s_tab[(q * 4 + 3) * NDP + j];
         if (MODE == MODE_DIAG) {
@@ -1134,11 +1136,11 @@ dg_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ kc, const T* _
       const T G5 = load_at(geo + 5 * (long)ncp, coff);
       const T adet = (C == 4) ? load_at(geo + 6 * (long)ncp, coff) : T(0);
       T kq[TC::KP];
+      const T* kct = kc ? kc + lanes::cell_data_index(NQ, 0, cc & ~15) : nullptr;
 #pragma unroll
       for (int k = 0; k < TC::KP; ++k)
-        kq[k] = kc ? load_at(kc + (long)(4 * k) * nc,
-                             ((uint32_t)lanes::kappa_lane_row(NQ, g, k) * (uint32_t)nc + (uint32_t)cc) *
-                                 (uint32_t)sizeof(T))
+        kq[k] = kc ? load_at(kct, (uint32_t)lanes::cell_data_index(NQ, 4 * k + lanes::kappa_lane_row(NQ, g, k), cc & 15) *
+                                      (uint32_t)sizeof(T))
                    : T(1);
       acc_t acc[TC::MT];
       __builtin_amdgcn_s_setprio(1);  // matrix-core section at raised wave priority
@@ -1352,7 +1354,10 @@ dg_grad_kernel(DGDev d, const T* __restrict__ u, const T* __restrict__ gv, T* __
         const T x_ = ag[i0 / 4][i0 % 4], y_ = ag[(i0 + 1) / 4][(i0 + 1) % 4], z_ = ag[(i0 + 2) / 4][(i0 + 2) % 4];
         const T val = s_qw[q] * (ux * (G0 * x_ + G1 * y_ + G2 * z_) + uy * (G1 * x_ + G3 * y_ + G4 * z_) +
                                  uz * (G2 * x_ + G4 * y_ + G5 * z_));
-        if (valid && q < NQ) dkc[(long)q * nc + cell] = accumulate ? dkc[(long)q * nc + cell] + val : val;
+        if (valid && q < NQ) {
+          const long di = lanes::cell_data_index(NQ, q, cell);
+          dkc[di] = accumulate ? dkc[di] + val : val;
+        }
       }
     }
     if (!dkf) continue;
@@ -1513,6 +1518,7 @@ hipError_t launch_dg(const DGDev& d, int prec, int ndof, int nq, int nqf, const 
 // both sides are read and written in whole rows (64 cells per workgroup;
 // every user row of nq values is contiguous).
 constexpr int kLayoutCells = 64;
+static_assert(kLayoutCells % 16 == 0, "layout blocks hold whole 16-cell tiles");
 constexpr int kLayoutMaxQ = 64;
 
 template <typename T>
@@ -1523,6 +1529,11 @@ __global__ void __launch_bounds__(256) layout_kernel(int to_user, const int* __r
   const int ncb = min(kLayoutCells, nc - c0);
   const int ld = nq + 1;  // odd row stride: the column reads hit distinct banks
   const int n = ncb * nq;
+  // library side: the block's 16-cell tiles are one contiguous run of
+  // nt 16 nq values (c0 is a multiple of 16); padding cells of the last tile
+  // are written as zero
+  const int nt = (ncb + 15) / 16;
+  const long lbase = lanes::cell_data_index(nq, 0, c0);
   if (!to_user) {
     // user rows (coalesced within each row) -> LDS [cell][q]
     for (int i = threadIdx.x; i < n; i += 256) {
@@ -1530,15 +1541,15 @@ __global__ void __launch_bounds__(256) layout_kernel(int to_user, const int* __r
       s[cl * ld + q] = static_cast<const double*>(src)[(long)perm[c0 + cl] * nq + q];
     }
     __syncthreads();
-    // LDS -> library rows [q][c0 .. c0 + ncb)
-    for (int i = threadIdx.x; i < n; i += 256) {
-      const int q = i / ncb, cl = i % ncb;
-      static_cast<T*>(dst)[(long)q * nc + c0 + cl] = (T)s[cl * ld + q];
+    // LDS -> library tiles [t][q][16]
+    for (int i = threadIdx.x; i < nt * 16 * nq; i += 256) {
+      const int t = i / (16 * nq), q = (i / 16) % nq, cl = 16 * t + i % 16;
+      static_cast<T*>(dst)[lbase + i] = cl < ncb ? (T)s[cl * ld + q] : T(0);
     }
   } else {
-    for (int i = threadIdx.x; i < n; i += 256) {
-      const int q = i / ncb, cl = i % ncb;
-      s[cl * ld + q] = (double)static_cast<const T*>(src)[(long)q * nc + c0 + cl];
+    for (int i = threadIdx.x; i < nt * 16 * nq; i += 256) {
+      const int t = i / (16 * nq), q = (i / 16) % nq, cl = 16 * t + i % 16;
+      if (cl < ncb) s[cl * ld + q] = (double)static_cast<const T*>(src)[lbase + i];
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n; i += 256) {

@@ -36,10 +36,19 @@ __host__ __device__ constexpr int pos_tail_row(int ndof, int g) {
   return n_tail(ndof) > 0 ? 16 + (g < n_tail(ndof) - 1 ? g : n_tail(ndof) - 1) : -1;
 }
 
-// Row of the coefficient array [n_q][n_cell] read for the lane's k-th
-// point (point g + 4 k), relative to the row base 4 k: lane group g in a
-// full group of four points, clamped to the last point in a partly used
-// last group (whose value is then masked).
+// Library layout of per-point cell data (coefficients, their gradients,
+// source samples): 16-cell tiles of consecutive library cells, each tile
+// holding its n_q points one after another with 16 values (one per cell)
+// per point, [ceil(n_cell / 16)][n_q][16].  A tile's data is one contiguous
+// run of 16 n_q values; the last tile is padded.
+__host__ __device__ constexpr long cell_data_index(int nq, int q, long cell) {
+  return ((cell >> 4) * nq + q) * 16 + (cell & 15);
+}
+__host__ __device__ constexpr long cell_data_size(int nq, long ncell) { return (long)nq * ((ncell + 15) / 16 * 16); }
+
+// Point of the lane's k-th group read from the per-point cell data, relative
+// to the group base 4 k: lane group g in a full group of four points, clamped
+// to the last point in a partly used last group (whose value is then masked).
 __host__ __device__ constexpr int kappa_lane_row(int nq, int g, int k) {
   return 4 * k + 3 < nq ? g : (g + 4 * k < nq - 1 ? g + 4 * k : nq - 1) - 4 * k;
 }

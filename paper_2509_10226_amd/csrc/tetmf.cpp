@@ -479,7 +479,9 @@ void check_lane_maps(int esize, int nd, int nq, int64_t ncp_max) {
     for (int k = 0; k < (nq + 3) / 4; ++k) {
       const int lr = lanes::kappa_lane_row(nq, g, k);
       if (lr < 0 || lr > 3 || 4 * k + lr >= nq) bad("coefficient row outside the rule");
-      if (((uint64_t)lr * n + n - 1) * esize >= lim) bad("coefficient offset beyond 32 bits");
+      // offset inside the cell's 16-cell tile of the per-point data
+      const long ci = lanes::cell_data_index(nq, 4 * k + lr, 15);
+      if (ci < 0 || ci >= 16L * nq || (uint64_t)ci * esize >= lim) bad("coefficient offset outside its tile");
     }
   }
   for (int j = 0; j < 32; ++j) {
@@ -1285,6 +1287,7 @@ extern "C" int tetmf_op_info(const tetmf_op* op, tetmf_info* info) {
   info->device_bytes = op->device_bytes();
   info->flops_per_backward = op->flops_bwd;
   info->bytes_per_backward = op->bytes_bwd;
+  info->n_cell_data = lanes::cell_data_size(op->nq, op->nc);
   return TETMF_OK;
 }
 
@@ -1422,6 +1425,16 @@ extern "C" int tetmf_apply_backward(tetmf_op* op, const void* u, const void* g, 
         (dkappa_face && (dkappa_face == u || dkappa_face == g || dkappa_face == du || dkappa_face == dkappa_cell)))
       return fail(TETMF_ERR_ALIAS, "tetmf_apply_backward: an output aliases another argument");
     if (op->prec == TETMF_BF16IN) return fail(TETMF_ERR_UNSUPPORTED, "tetmf_apply_backward: BF16 operands");
+    if (dkappa_cell && op->nc % 16 != 0) {
+      // the padding cells of the last 16-cell tile get zeros (the kernels
+      // write real cells only); a fill kernel, so that the call stays
+      // capturable in a HIP graph
+      DeviceScope dsz(op->device);
+      const long last = lanes::cell_data_index(op->nq, 0, op->nc & ~(int64_t)15);
+      check_hip(vec_fill(kernel_prec(op), (char*)dkappa_cell + last * op->esize(), 0.0, 16L * op->nq,
+                         (hipStream_t)stream),
+                "fill");
+    }
     if (op->kind == TETMF_CG) {
       if (!du && !dkappa_cell) return TETMF_OK;
       return run_cg(op, MODE_BACKWARD, u, g, kappa_cell, du, dkappa_cell, stream);

@@ -118,3 +118,31 @@ def test_dg_backward_small(mesh):
     dkc_o, dkf_o = oracle.dg_kappa_grad(xyz, tets, 2, qp, qw, fp, fw, u, g, bc="dirichlet")
     assert rel_err(op.cell_data_to_user(dk).cpu().numpy(), dkc_o) <= 1e-12
     assert rel_err(dkf.cpu().numpy().T, dkf_o) <= 1e-12
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_cell_data_layout_tiles(precision):
+    """Per-point cell data in library layout: point q of library cell i at
+    ((i / 16) n_q + q) 16 + i % 16, the padding of the partly used last tile
+    zero, and the conversion back to user layout exact (3^3 x 6 = 162 cells:
+    ten full tiles and one with two cells)."""
+    import paper_2509_10226_amd as tm
+    xyz, tets = synth.kuhn_cube_mesh(3, 0.15, 0)
+    qp, qw = synth.tet_rule(4)
+    op = tm.Operator(tm.Mesh(xyz, tets), 2, (qp, qw), precision=precision)
+    nc, nq = tets.shape[0], qw.size
+    assert nc % 16 != 0
+    assert op.n_cell_data == nq * 16 * ((nc + 15) // 16)
+    data = synth.uniform(4, synth.STREAM_KAPPA_CELL, nc * nq).reshape(nc, nq)
+    if precision != "f64":
+        data = data.astype(np.float32).astype(np.float64)
+    kl = op.cell_data_to_library(torch.from_numpy(data).cuda())
+    assert kl.numel() == op.n_cell_data
+    cp, _, _ = op.numbering()
+    lib = kl.double().cpu().numpy()
+    cells = np.arange(nc)
+    expected = np.zeros(op.n_cell_data)
+    for q in range(nq):
+        expected[op.cell_data_index(q, cells)] = data[cp, q]
+    assert np.array_equal(lib, expected)
+    assert np.array_equal(op.cell_data_to_user(kl).cpu().numpy(), data)

@@ -52,12 +52,12 @@ def test_backward_errors(ops):
     s = tm._stream()
     u = torch.zeros(cg.n_vec, dtype=torch.float64, device="cuda")
     g = torch.zeros_like(u)
-    dk = torch.zeros(cg.n_q * cg.n_cell, dtype=torch.float64, device="cuda")
+    dk = torch.zeros(cg.n_cell_data, dtype=torch.float64, device="cuda")
     assert L.tetmf_apply_backward(cg._h, _p(u), _p(g), None, None, _p(u), None, None, s) == ALIAS
     assert L.tetmf_apply_backward(cg._h, _p(u), _p(g), None, None, None, _p(dk), _p(dk), s) == INVALID
     ud = torch.zeros(dg.n_vec, dtype=torch.float64, device="cuda")
     gd = torch.zeros_like(ud)
-    dkc = torch.zeros(dg.n_q * dg.n_cell, dtype=torch.float64, device="cuda")
+    dkc = torch.zeros(dg.n_cell_data, dtype=torch.float64, device="cuda")
     assert L.tetmf_apply_backward(dg._h, _p(ud), _p(gd), None, None, None, _p(dkc), _p(dkc), s) == ALIAS
     ub = torch.zeros(bf.n_vec, dtype=torch.float32, device="cuda")
     assert L.tetmf_apply_backward(bf._h, _p(ub), _p(ub.clone()), None, None, _p(ub.clone()), None, None,
@@ -71,7 +71,7 @@ def test_diagonal_load_layout_errors(ops):
     d = torch.zeros(dg.n_vec, dtype=torch.float64, device="cuda")
     assert L.tetmf_diagonal(dg._h, None, None, _p(d), s) == UNSUPPORTED
     assert L.tetmf_load_vector(dg._h, None, _p(d), s) == UNSUPPORTED
-    x = torch.zeros(cg.n_q * cg.n_cell, dtype=torch.float64, device="cuda")
+    x = torch.zeros(cg.n_cell_data, dtype=torch.float64, device="cuda")
     assert L.tetmf_cell_data_layout(cg._h, _p(x), _p(x), 0, s) == ALIAS
 
 

@@ -236,7 +236,7 @@ def test_c4_backward_and_finite_differences():
         vals = []
         for sgn in (1.0, -1.0):
             kk = kl.clone()
-            kk[q, le] += sgn * h
+            kk[op.cell_data_index(q, int(le))] += sgn * h
             vv = op.apply(ut, kk).cpu().numpy()[cell_dofs]
             vals.append(vv)
         vp, vm = vals
