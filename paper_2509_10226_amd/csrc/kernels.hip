@@ -503,12 +503,16 @@ template <typename T, int NQ, int C>
 __device__ inline void point_geo(const T* __restrict__ geo, int ncp, const T* __restrict__ kappa, int nc, int k,
                                  int g, int cell, int cc, T dep, T (&G)[8]) {
   const int q = min(g + 4 * k, NQ - 1);
-  uint32_t off = ((uint32_t)(q - 4 * k) * (uint32_t)ncp + (uint32_t)cell) * (uint32_t)sizeof(T);
+  // geometry: the cell's 16-cell tile (the geometry is padded to whole
+  // blocks) as the base and the point and cell inside it as the offset
+  uint32_t off = (uint32_t)lanes::curved_geo_index(NQ, 0, q, cell & 15) * (uint32_t)sizeof(T);
   // coefficient: tile base of the clamped cell and an offset inside its tile
   uint32_t kof = (uint32_t)lanes::cell_data_index(NQ, q, cc & 15) * (uint32_t)sizeof(T);
   asm volatile("" : "+v"(off), "+v"(kof) : "v"(dep));
+  const T* gt = geo + lanes::curved_geo_index(NQ, 0, 0, cell & ~15);
+  (void)ncp;
 #pragma unroll
-  for (int c = 0; c < (C == 4 ? 7 : 6); ++c) G[c] = load_at(geo + ((long)c * NQ + 4 * k) * ncp, off);
+  for (int c = 0; c < (C == 4 ? 7 : 6); ++c) G[c] = load_at(gt + c * NQ * 16, off);
   if (C != 4) G[6] = T(0);
   G[7] = kappa ? load_at(kappa + lanes::cell_data_index(NQ, 0, cc & ~15), kof) : T(1);
   (void)nc;
@@ -854,9 +858,10 @@ __global__ void __launch_bounds__(kThreads) cg_vec_kernel(CGDev d, const T* __re
       if (cell >= nc) continue;
       T acc = 0;
       for (int q = 0; q < NQ; ++q) {
-        // geometry row (c, q) of curved cells, or row c of straight ones
-        const long gr = CURV ? (long)q * ncp + cell : (long)cell;
-        const long gs = CURV ? (long)NQ * ncp : (long)ncp;
+        // geometry (c, q) of curved cells (16-cell tiles), or row c of
+        // straight ones
+        const long gr = CURV ? lanes::curved_geo_index(NQ, 0, q, cell) : (long)cell;
+        const long gs = CURV ? (long)NQ * 16 : (long)ncp;
         const T G0 = geo[gr], G1 = geo[gs + gr], G2 = geo[2 * gs + gr];
         const T G3 = geo[3 * gs + gr], G4 = geo[4 * gs + gr], G5 = geo[5 * gs + gr];
         const T adet = geo[6 * gs + gr];

@@ -46,6 +46,13 @@ __host__ __device__ constexpr long cell_data_index(int nq, int q, long cell) {
 }
 __host__ __device__ constexpr long cell_data_size(int nq, long ncell) { return (long)nq * ((ncell + 15) / 16 * 16); }
 
+// Per-point geometry of curved cells (7 values per point: G and |det J|) in
+// 16-cell tiles, [ncp / 16][7][n_q][16]: one tile's geometry is one
+// contiguous run of 7 16 n_q values.
+__host__ __device__ constexpr long curved_geo_index(int nq, int c, int q, long cell) {
+  return (((cell >> 4) * 7 + c) * nq + q) * 16 + (cell & 15);
+}
+
 // Point of the lane's k-th group read from the per-point cell data, relative
 // to the group base 4 k: lane group g in a full group of four points, clamped
 // to the last point in a partly used last group (whose value is then masked).

@@ -595,9 +595,10 @@ std::vector<double> cell_geometry(const tetmf_mesh& m, const std::vector<int32_t
   return geo;
 }
 
-// Per-point geometry of curved cells [7][nq][ncp]: G_q = |det J_q| J_q^-1
-// J_q^-T and |det J_q| for each library cell and rule point, from the user's
-// Jacobians [n_cell][nq][3][3] (user cell order).
+// Per-point geometry of curved cells, in 16-cell tiles [ncp / 16][7][nq][16]
+// (lanes::curved_geo_index): G_q = |det J_q| J_q^-1 J_q^-T and |det J_q| for
+// each library cell and rule point, from the user's Jacobians
+// [n_cell][nq][3][3] (user cell order); padding cells hold zeros.
 std::vector<double> point_geometry(const double* jac, const std::vector<int32_t>& perm, int nq, int64_t ncp) {
   std::vector<double> geo((size_t)7 * nq * ncp, 0.0);
   for (int64_t i = 0; i < (int64_t)perm.size(); ++i)
@@ -616,7 +617,7 @@ std::vector<double> point_geometry(const double* jac, const std::vector<int32_t>
           G[x][y] = adet * sum;
         }
       const double vals[7] = {G[0][0], G[0][1], G[0][2], G[1][1], G[1][2], G[2][2], adet};
-      for (int k = 0; k < 7; ++k) geo[((size_t)k * nq + q) * ncp + i] = vals[k];
+      for (int k = 0; k < 7; ++k) geo[(size_t)lanes::curved_geo_index(nq, k, q, i)] = vals[k];
     }
   return geo;
 }
