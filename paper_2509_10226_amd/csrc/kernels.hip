@@ -537,7 +537,7 @@ struct MinWaves {
 
 // Curved cells read a geometry and a coefficient per point.  FP64: all of a
 // tile's points are requested before its interpolation (588 -> 582 us at
-// 64^3 x 6, no scratch in any curved FP64 kernel).  FP32: one point at a
+// 64^3 x 6), except in the Helmholtz backward, which would spill with them.  FP32: one point at a
 // time, each request tied to the previous point's result (all at once:
 // 330 -> 363 us).
 template <typename T, bool CURV>
@@ -713,7 +713,10 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE, CURV>::value, 8))) cg
             gb[BWD ? ks : 0] = j < NDOF ? y : T(0);
           }
         }
-        constexpr bool kAhead = CurvAhead<T, CURV>::value;
+        // (not for the curved Helmholtz backward, which holds the second
+        // interpolation's four values per item as well: all points' geometry
+        // at once would spill there)
+        constexpr bool kAhead = CurvAhead<T, CURV>::value && !(BWD && C == 4);
         T Gpre[kAhead ? KP : 1][8];
         if constexpr (kAhead) {
           const int cc = valid ? cell : nc - 1;
