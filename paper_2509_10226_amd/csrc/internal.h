@@ -33,7 +33,7 @@ struct CGDev {
   int n_partials;         // partial sums per component
   double sigma;           // mass coefficient
   const void* geo;        // [7][ncp]: G00 G01 G02 G11 G12 G22 (= |detJ| J^-1 J^-T), |detJ|;
-                          // curved: [7][nq][ncp], the same per rule point
+                          // curved: [ncp/16][7][nq][16] (16-cell tiles), the same per rule point
   const void* tab;        // basis table, layout chosen by the precision (see kernels.hip)
   const void* qw;         // [4*MT] quadrature weights, zero beyond nq
   const int* blk_priv_start;  // [n_blocks] first id of the block's private DoF range

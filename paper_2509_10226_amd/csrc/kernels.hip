@@ -491,9 +491,10 @@ __device__ inline void cg_reduce(const CGDev& d, const T* __restrict__ s_slot, i
   }
 }
 
-// Geometry of one rule point of the lane's cell for curved cells: row
-// (c, q) of the [7][NQ][ncp] table, q = g + 4k clamped to the rule, read
-// with a wave-uniform row base (c, 4k) and a 32-bit lane offset.
+// Geometry of one rule point of the lane's cell for curved cells: value
+// (c, q) of the cell's 16-cell tile of the geometry ([ncp / 16][7][NQ][16]),
+// q = g + 4k clamped to the rule, read with the tile as the base and a
+// 32-bit offset inside it.
 // dep: a value computed just before; the offset passes through an empty asm
 // that depends on it, so the loads are issued there and not hoisted (the
 // matrix-core tiles need the registers).
@@ -660,7 +661,8 @@ __attribute__((amdgpu_waves_per_eu(MinWaves<T, NDOF, MODE, CURV>::value, 8))) cg
           for (int c = 0; c < 6; ++c) Gc[c] = load_at(geo + c * (long)ncp, coff);
           Gc[6] = (C == 4) ? load_at(geo + 6 * (long)ncp, coff) : T(0);
         }
-        // coefficient at this lane's points q = g + 4k (row q of [NQ][nc]),
+        // coefficient at this lane's points q = g + 4k (point q of the cell's
+        // 16-cell tile of the per-point data),
         // from a clamped (always valid) address and masked afterwards
         T kq[KP];
         if (CURV) {

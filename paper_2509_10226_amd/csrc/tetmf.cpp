@@ -488,7 +488,7 @@ void check_lane_maps(int esize, int nd, int nq, int64_t ncp_max) {
     const int o = lanes::operand_row(nd, j);
     if (o < 0 || o >= nd) bad("operand row outside the cell's DoFs");
   }
-  // geometry (cell * size, curved: point row below 4 from a row base) and
+  // geometry (cell * size; curved: an offset inside a 16-cell tile) and
   // the block-index staging (2 (j ncp + cell in block))
   if ((4 * n - 1) * esize >= lim) bad("geometry offset beyond 32 bits");
   if (2 * ((uint64_t)(nd - 1) * n + 255) >= lim) bad("index staging offset beyond 32 bits");
