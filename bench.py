@@ -677,7 +677,8 @@ def main():
     SETTLE_S = args.settle
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the operator shards by "
-              "cell partition with one halo exchange per apply, which this build does not run).", file=sys.stderr)
+              "cell partition with one exchange of interface partial sums per apply; that path is not implemented).",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
